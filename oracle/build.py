@@ -1,0 +1,28 @@
+"""Build the FP64 CPU oracle shared library (test infrastructure only).
+
+The oracle is plain C11 with OpenMP, compiled without fast-math so that every operation is the
+IEEE double operation written in the source.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["oracle_core.c", "oracle_field.c", "oracle_trace.c", "oracle_render.c"]
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+           "-shared", "-Wall", "-Wextra", "-Wno-unused-parameter", "-D_GNU_SOURCE", "-o", LIB + ".tmp"]
+    cmd += [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)
+    print(LIB)

@@ -1,0 +1,197 @@
+/*
+ * FP64 CPU oracle for Photon Field Networks (Bauer, Wu, Ma; arXiv 2304.07338).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that the
+ * GPU path is checked against.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no source, header,
+ * table or helper with the HIP library; both sides are written independently
+ * from the paper and from the published definitions they cite.
+ *
+ * Everything is double precision.  Inputs that are random draws of the method
+ * (photon emission, scattering, sub-pixel jitter, training batches) come from
+ * Philox4x32-10 (Salmon et al., SC'11), implemented here from its published
+ * definition.
+ *
+ * Geometry: the world is the unit cube [0,1]^3 (Section 3.1); every length and
+ * every extinction coefficient is in cube units.
+ */
+#ifndef PFN_ORACLE_H
+#define PFN_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------- Counter-based RNG ---------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* uint32 -> (0,1): ((x >> 9) + 0.5) * 2^-23, exact in binary32 and binary64 */
+double orc_u01(uint32_t x);
+/* Fill n uniforms of stream (seed, item, stream_id) starting at draw 0. */
+void orc_uniforms(uint64_t seed, uint64_t item, uint32_t stream_id, int n, double *out);
+
+/* ---------------- Phase function (Section 3.2, Henyey-Greenstein) ---------------- */
+double orc_hg_eval(double g, double mu);
+double orc_hg_sample_mu(double g, double u);
+void orc_hg_sample_dir(double g, const double w[3], double u1, double u2, double out[3]);
+
+/* ---------------- Scene ---------------- */
+typedef struct {
+  const double *density; /* [nz][ny][nx], x fastest, values in [0,1] */
+  int nx, ny, nz;
+  const double *tf;      /* [256][4] RGBA; RGB = single-scattering albedo, A = opacity */
+  double ext_scale;      /* sigma_t = ext_scale * A, per cube length */
+  const double *lights;  /* [n_lights][6]: position xyz, radiant intensity rgb */
+  int n_lights;
+} orc_scene;
+
+double orc_density(const orc_scene *s, const double x[3]);
+void orc_transfer(const orc_scene *s, double rho, double *sigma_t, double albedo[3]);
+double orc_majorant(const orc_scene *s);
+int orc_clip_cube(const double o[3], const double d[3], double *t0, double *t1);
+double orc_shadow_transmittance(const orc_scene *s, const double x[3], const double p[3],
+                                double step);
+
+/* ---------------- Photon cache (isotropic, per HG bin) ---------------- */
+typedef struct {
+  const double *data;  /* [n_bins][res^3][3], x fastest */
+  int n_bins;
+  const double *g_bins; /* ascending */
+  int res;
+} orc_cache;
+void orc_cache_gather(const orc_cache *c, const double x[3], double g, double out[3]);
+
+/* ---------------- Photon field (Sections 3.1, 3.3.2, 3.4) ---------------- */
+typedef struct {
+  int levels;        /* 16 */
+  int feats;         /* features per level (2) */
+  int base_res;      /* 16 */
+  double growth;     /* 1.5 */
+  int log2_table;    /* 19 */
+  int hidden_layers; /* 3 */
+  int width;         /* 64 */
+  double psi;        /* 5 */
+} orc_field_desc;
+
+typedef struct {
+  size_t pos_off[33], dir_off[33]; /* per-level entry offsets (in entries), [levels] = total */
+  int pos_res[32], dir_res[32];
+  int pos_dense[32], dir_dense[32];
+  size_t pos_params, dir_params;   /* number of floats */
+  size_t mlp_off;                  /* float offset of the first weight matrix */
+  size_t w_off[8];                 /* float offset of each weight matrix */
+  int w_rows[8], w_cols[8];
+  int n_mats;
+  int n_in;                        /* network input width */
+  size_t n_params;
+} orc_field_layout;
+
+int orc_field_make_layout(const orc_field_desc *d, orc_field_layout *L);
+size_t orc_field_num_params(const orc_field_desc *d);
+/* rounding of parameters before use: 0 none, 1 binary16 RNE, 2 bfloat16 RNE */
+void orc_field_forward(const orc_field_desc *d, const double *params, int rounding, int64_t n,
+                       const double *xyz, const double *dir, const double *g, double *out_lp);
+double orc_field_loss_grad(const orc_field_desc *d, const double *params, int rounding, int64_t n,
+                           const double *xyz, const double *dir, const double *g,
+                           const double *target, double *grad /* n_params, overwritten */);
+/* Encoding of one input: z has layout.n_in entries. */
+void orc_field_encode(const orc_field_desc *d, const double *params, int rounding, const double x[3],
+                      const double w[3], double g, double *z);
+double orc_round_half(double v);
+double orc_round_bf16(double v);
+
+/* Log target encoding, Eq. (6), and its inverse, Eq. (7). */
+double orc_log_encode(double v, double psi);
+double orc_exp_decode(double lp, double psi);
+
+/* ---------------- Training (Section 3.5.1) ---------------- */
+void orc_adam_step(int64_t n, double *param, const double *grad, double *m, double *v, int64_t t,
+                   double lr, double beta1, double beta2, double eps);
+double orc_lr_at(int64_t step, double lr0, double decay, int64_t start_step, int64_t interval);
+void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache, double kappa,
+                     double psi, double *xyz, double *dir, double *g, int *bin, double *target);
+
+/* ---------------- Photon tracing (Algorithm 1) ---------------- */
+typedef struct {
+  uint64_t n_photons;
+  int n_bins;
+  double g_bins[8];
+  int max_collisions;   /* 8 */
+  int rr_start;         /* first collision index at which Russian roulette runs; <=0 disables */
+  uint64_t seed;
+} orc_trace_params;
+
+typedef struct {
+  double emitted[3], entered[3], escaped[3], escaped_uncollided[3], absorbed[3], truncated[3],
+      rr_killed[3], stored[3];
+  double collisions;   /* total real collisions */
+  double null_events;  /* total null collisions */
+  uint64_t n_records;
+} orc_trace_stats;
+
+/* Trace photons [first, first+count).  Records (if rec_* != NULL) are written in photon order,
+ * collision order; *n_rec returns how many were produced (capacity cap).  rec_photon gets the id. */
+void orc_trace(const orc_scene *s, const orc_trace_params *p, uint64_t first, uint64_t count,
+               orc_trace_stats *st, uint64_t cap, double *rec_x, double *rec_w, double *rec_pow,
+               int *rec_bin, uint64_t *rec_photon, uint64_t *n_rec);
+
+/* Splat records into an isotropic per-bin cache [n_bins][res^3][3]; returns kappa = max. */
+double orc_splat_cache(const orc_scene *s, int64_t n_rec, const double *rec_x, const double *rec_pow,
+                       const int *rec_bin, int res, int n_bins, double *cache_out);
+
+/* ---------------- Ray marcher (Sections 3.1 and 3.6) ---------------- */
+typedef struct {
+  double eye[3], target[3], up[3];
+  double fov_y_deg;
+  int width, height;
+} orc_camera;
+
+enum { ORC_IND_NONE = 0, ORC_IND_CACHE = 1, ORC_IND_FIELD = 2 };
+enum { ORC_DIR_SHADOW = 0, ORC_DIR_LIGHTVOL = 1 };
+
+typedef struct {
+  int spp;
+  double step_voxels;
+  int max_steps;
+  double t_min;
+  int field_stride;
+  double g;
+  int indirect;
+  int direct;
+  int light_mask;   /* bit l set -> light l contributes; 0 = all lights */
+  double lv_step_voxels; /* march step used to build the light transmittance grid */
+  uint64_t seed;
+} orc_render_params;
+
+typedef struct {
+  const orc_field_desc *desc;
+  const double *params;
+  int rounding;
+  double kappa;
+} orc_field;
+
+void orc_camera_ray(const orc_camera *c, double px, double py, double o[3], double d[3]);
+/* Render selected pixels (indices into the row-major width*height image); out is [n_pix][3]. */
+void orc_render_pixels(const orc_scene *s, const orc_camera *c, const orc_render_params *p,
+                       const orc_cache *cache, const orc_field *field, int64_t n_pix,
+                       const int64_t *pix, double *out);
+/* Light transmittance grid value at grid point (i,j,k) of a res^3 grid, light l. */
+double orc_lightvol_point(const orc_scene *s, int res, int l, int i, int j, int k, double step);
+int orc_lightvol_res(int n);
+
+/* ---------------- Path tracer (Section 4.3 baseline) ---------------- */
+void orc_pt_pixels(const orc_scene *s, const orc_camera *c, int spp, int max_bounces, double g,
+                   int rr_start, uint64_t seed, int light_mask, int64_t n_pix, const int64_t *pix,
+                   double *out);
+
+/* ---------------- Metrics ---------------- */
+void orc_image_error(int64_t n, const double *img, const double *ref, double *rmse, double *rel_rmse,
+                     double *psnr);
+
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
