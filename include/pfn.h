@@ -1,0 +1,246 @@
+/*
+ * pfn.h — C ABI of the MI355X (gfx950) photon-field library.
+ *
+ * Photon Field Networks (Bauer, Wu, Ma; arXiv 2304.07338): a learned field P(x, g, w) -> RGB
+ * (Eq. 2) that stands for the indirect in-scattered radiance L_i of Eq. (3)/(4), trained on
+ * multi-phase photon caches (Section 3.2, Algorithm 1) and queried by a renderer that adds it to
+ * direct light (Section 3.6).  The three top-level calls follow the paper's pipeline figure:
+ * trace a multi-phase photon cache, train the field, render frames (retrain when the transfer
+ * function or the lights change).
+ *
+ * Conventions for every call:
+ *  - Return value: PFN_OK (0) or a negative pfn_status.  On error, pfn_last_error() describes it;
+ *    arguments are validated before anything is launched, so an INVALID_ARG call has no effect.
+ *  - Pointers named dev_* are device pointers on the context's device, owned by the caller and
+ *    only borrowed for the call (the library never frees them and keeps no reference after the
+ *    call returns unless stated).  host_* pointers are host memory.
+ *  - Work is enqueued on the context stream.  Calls that return host_* results synchronise that
+ *    stream before returning; dev_* results are ready in stream order (or after pfn_sync).
+ *  - The unit cube [0,1]^3 is the world; lengths and extinction are in cube units.  Density
+ *    volumes are [nz][ny][nx] with x fastest; voxel (i,j,k) has its centre at ((i+.5)/nx, ...).
+ *  - A context is bound to one device and one stream; it is not thread-safe.
+ */
+#ifndef PFN_H
+#define PFN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFN_OK = 0,
+  PFN_ERR_INVALID_ARG = -1,
+  PFN_ERR_OUT_OF_MEMORY = -2,
+  PFN_ERR_HIP = -3,
+  PFN_ERR_NOT_READY = -4,   /* a prerequisite (volume, cache, field, ...) is missing */
+  PFN_ERR_UNSUPPORTED = -5,
+  PFN_ERR_NUMERIC = -6      /* NaN or Inf met (e.g. in the training loss) */
+} pfn_status;
+
+typedef enum { PFN_F32 = 0, PFN_F16 = 1, PFN_BF16 = 2 } pfn_dtype;
+
+typedef struct pfn_context pfn_context;
+
+/* ------------------------------------------------------------------ context */
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is used for all work;
+ * NULL makes the library create and own a stream. */
+pfn_status pfn_create(int device, void *hip_stream, pfn_context **out);
+/* Free every context-owned buffer (volume bricks, caches, records, fields, optimiser state). */
+void pfn_destroy(pfn_context *ctx);
+/* Text of the last error on this context; valid until the next call on it. */
+const char *pfn_last_error(const pfn_context *ctx);
+pfn_status pfn_sync(pfn_context *ctx);
+/* Replace the stream used for subsequent work (NULL = the library-owned stream). */
+pfn_status pfn_set_stream(pfn_context *ctx, void *hip_stream);
+
+/* ------------------------------------------------------------------ scene */
+/* Scalar volume (Algorithm 1: Volume(x,y,z)): dev_density holds nx*ny*nz values of `dtype`
+ * (PFN_F32 or PFN_F16) in [0,1], copied into a context-owned brick layout.  Sizes 2..4096. */
+pfn_status pfn_set_volume(pfn_context *ctx, const void *dev_density, pfn_dtype dtype, int nx,
+                          int ny, int nz);
+/* Transfer function (Algorithm 1: TransferFunction(sample)): 256 RGBA entries sampled at
+ * density e/255; RGB is the single-scattering albedo, A the opacity; extinction
+ * sigma_t = extinction_scale * A per cube length.  Values must be finite; RGB, A in [0,1]. */
+pfn_status pfn_set_transfer_function(pfn_context *ctx, const float *host_rgba_256x4,
+                                     float extinction_scale);
+typedef struct {
+  float pos[3];       /* cube units */
+  float intensity[3]; /* radiant intensity (power per steradian), RGB */
+} pfn_point_light;
+/* Point lights (1..4).  Replacing lights or the transfer function invalidates the light volume. */
+pfn_status pfn_set_lights(pfn_context *ctx, const pfn_point_light *host_lights, int n_lights);
+/* Light-transmittance grid for direct light (one channel per light) at half the volume
+ * resolution per axis, each value the exact shadow-march transmittance from the grid point to
+ * the light with `step_voxels` steps (global shadows, Section 4.3). */
+pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels);
+
+/* ------------------------------------------------------------------ 1. photon cache */
+typedef struct {
+  uint64_t n_photons;   /* photon paths; split evenly over lights and HG bins (Section 4.4) */
+  int n_bins;           /* |G|, 1..8 */
+  float g_bins[8];      /* the phase pool G, ascending, |g| <= 0.95 */
+  int cache_res;        /* cache grid resolution per axis, 2..512 */
+  int max_collisions;   /* real collisions per photon path, 1..64 */
+  int rr_start;         /* Russian roulette from this collision on; <= 0 disables it */
+  uint64_t seed;
+} pfn_trace_params;
+
+typedef struct {
+  uint64_t n_records;          /* stored photon interactions (collisions 2..max) */
+  uint64_t n_records_dropped;  /* beyond the record buffer (0 unless the cap was hit) */
+  double emitted[3], entered[3], escaped[3], escaped_uncollided[3], absorbed[3], truncated[3],
+      rr_killed[3], stored[3]; /* power tallies (FP64) */
+  double collisions, null_events;
+  double kappa;                /* max cache value: the normaliser of the log target encoding */
+} pfn_trace_stats;
+
+/* Multi-phase photon tracing (Algorithm 1) and the isotropic per-bin photon cache built from its
+ * records: the collision estimator Phi/sigma_t splatted cloud-in-cell and divided by
+ * 4*pi*V_cell.  Requires volume, transfer function and lights.  Synchronises. */
+pfn_status pfn_trace_photon_cache(pfn_context *ctx, const pfn_trace_params *params,
+                                  pfn_trace_stats *host_stats);
+/* Copy up to `capacity` photon records of the last trace in photon order:
+ * position xyz, incident direction xyz, incident power RGB (float x3 each), HG bin, photon id.
+ * Any output pointer may be NULL.  *host_count receives the number copied.  Synchronises. */
+pfn_status pfn_get_records(pfn_context *ctx, float *dev_x, float *dev_w, float *dev_power,
+                           int32_t *dev_bin, int64_t *dev_photon, uint64_t capacity,
+                           uint64_t *host_count);
+/* Cache as [n_bins][res][res][res][3] float (x fastest). */
+pfn_status pfn_get_cache(pfn_context *ctx, float *dev_out, size_t n_floats);
+pfn_status pfn_set_cache(pfn_context *ctx, const float *dev_in, int n_bins,
+                         const float *host_g_bins, int res, double kappa);
+pfn_status pfn_cache_info(pfn_context *ctx, int *host_n_bins, int *host_res, double *host_kappa);
+
+/* ------------------------------------------------------------------ 2. photon field */
+typedef struct {
+  int levels;          /* grid levels (1..16) */
+  int feats_per_level; /* 2 */
+  int base_res;        /* coarsest grid resolution */
+  float growth;        /* per-level resolution factor; N_l = floor(base_res * growth^l) */
+  int log2_table;      /* hashed-level table size 2^log2_table (dense levels are exact) */
+  int hidden_layers;   /* ReLU hidden layers (1..7) of width 64, no biases, linear output */
+  int width;           /* 64 */
+  float psi;           /* log target encoding precision (Eq. 6/7) */
+} pfn_field_desc;
+
+/* Select the field slot (0..7) that the field calls below act on; each slot holds its own
+ * parameters, optimiser state and kappa.  Renders use the slot in their parameters. */
+pfn_status pfn_field_select(pfn_context *ctx, int slot);
+/* Initialise the selected slot: grid features U(-1e-4, 1e-4), weights Glorot-uniform. */
+pfn_status pfn_field_init(pfn_context *ctx, const pfn_field_desc *desc, uint64_t seed);
+pfn_status pfn_field_num_params(pfn_context *ctx, size_t *host_n);
+/* Parameter vector (FP32 master copy): [position grid][direction grid][W_0]...[W_H], each grid
+ * level's entries holding feats_per_level consecutive features, each W row-major (out x in). */
+pfn_status pfn_field_get_params(pfn_context *ctx, float *dev_out, size_t n);
+pfn_status pfn_field_set_params(pfn_context *ctx, const float *dev_in, size_t n);
+pfn_status pfn_field_set_kappa(pfn_context *ctx, double kappa);
+/* Field inference (Eq. 2) at n points: xyz in [0,1]^3, unit directions (the view direction
+ * pointing back along the ray), g.  Writes the raw network output L' (n x 3) and, if dev_rgb is
+ * not NULL, the decoded radiance kappa * 10^(-psi L') (Eq. 7).  precision: arithmetic of the
+ * grid features and MLP (F32, F16 or BF16 matrix cores, FP32 accumulation). */
+pfn_status pfn_field_query(pfn_context *ctx, pfn_dtype precision, const float *dev_xyz,
+                           const float *dev_dir, const float *dev_g, int64_t n,
+                           float *dev_lprime, float *dev_rgb);
+/* L2 loss mean((L' - target)^2) over n x 3 outputs and its gradient with respect to every
+ * parameter (same layout as the parameter vector), FP32 accumulation.  Synchronises. */
+pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype precision, const float *dev_xyz,
+                                      const float *dev_dir, const float *dev_g,
+                                      const float *dev_target, int64_t n, double *host_loss,
+                                      float *dev_grad);
+
+typedef struct {
+  int steps;            /* training steps */
+  int log2_batch;       /* samples per step = 2^log2_batch (8..22) */
+  float lr, beta1, beta2, eps;
+  float decay;          /* lr *= decay at decay_start and every decay_interval steps after */
+  int decay_start, decay_interval;
+  pfn_dtype precision;  /* F16 or BF16 matrix cores, or F32 */
+  uint64_t seed;
+} pfn_train_params;
+
+/* Section 3.5: each step draws a fresh batch (uniform x, uniform direction, g from the cache
+ * bins; target = Eq. 6 of the cache value / kappa), runs forward, L2 loss, backward and Adam.
+ * Requires a cache and an initialised field.  host_loss_history (steps floats) may be NULL.
+ * Synchronises. */
+pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *params,
+                           float *host_loss_history);
+/* The training-batch generator alone (for checking): step `step`'s n samples. */
+pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
+                           float *dev_xyz, float *dev_dir, float *dev_g, int32_t *dev_bin,
+                           float *dev_target);
+/* One Adam step (bias-corrected, step t >= 1) on the selected field with gradient dev_grad. */
+pfn_status pfn_field_adam_step(pfn_context *ctx, const float *dev_grad, int64_t t, float lr,
+                               float beta1, float beta2, float eps);
+
+/* ------------------------------------------------------------------ 3. rendering */
+typedef struct {
+  float eye[3], target[3], up[3];
+  float fov_y_deg;
+  int width, height;
+} pfn_camera;
+
+typedef enum { PFN_INDIRECT_NONE = 0, PFN_INDIRECT_CACHE = 1, PFN_INDIRECT_FIELD = 2 } pfn_indirect;
+typedef enum { PFN_DIRECT_SHADOW_RAYS = 0, PFN_DIRECT_LIGHT_VOLUME = 1 } pfn_direct;
+
+typedef struct {
+  int spp;              /* samples per pixel (1 = pixel centre, step midpoints) */
+  float step_voxels;    /* march step in voxels of the largest volume dimension */
+  int max_steps;        /* step cap per ray */
+  float t_min;          /* stop when transmittance < t_min (0 = never) */
+  int field_stride;     /* indirect light is evaluated every field_stride steps and held */
+  float g;              /* HG anisotropy of the render, |g| <= 0.95 */
+  pfn_indirect indirect;
+  pfn_direct direct;
+  pfn_dtype field_precision;
+  int light_mask;       /* bit l selects light l; 0 = all lights */
+  int field_slot;       /* field used when indirect = FIELD */
+  uint64_t seed;        /* sub-pixel jitter when spp > 1 */
+} pfn_render_params;
+
+/* Ray-marched frame (Section 3.6 allows the field inside a ray marcher): per step the transfer
+ * function, alpha = 1 - exp(-sigma_t l), direct in-scattered light from the point lights
+ * (shadow rays or light volume), indirect in-scattered light from the field, the cache or none,
+ * composited front to back: C += T alpha albedo (L_d + L_i); T *= exp(-sigma_t l).
+ * Output dev_rgb_out: height x width x 3 floats (row 0 at the top). */
+pfn_status pfn_render_frame(pfn_context *ctx, const pfn_camera *cam, const pfn_render_params *p,
+                            float *dev_rgb_out);
+
+typedef struct {
+  pfn_camera cam;
+  pfn_render_params params;
+  float *dev_rgb_out;
+} pfn_render_job;
+/* Many frames of uneven sizes in one persistent launch (shared volume, per-job camera, lights,
+ * g and field slot).  All jobs must share indirect/direct mode and field precision. */
+pfn_status pfn_render_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs);
+
+/* Monte Carlo volumetric path tracer (the baseline of Section 4.3): delta tracking, next-event
+ * estimation with ratio tracking, HG sampling, at most max_bounces collisions. */
+pfn_status pfn_render_path_traced(pfn_context *ctx, const pfn_camera *cam, int spp,
+                                  int max_bounces, float g, int rr_start, int light_mask,
+                                  uint64_t seed, float *dev_rgb_out);
+
+/* RMSE, RMSE / mean(ref) and 20 log10(max(ref) / RMSE) over n floats, accumulated in FP64.
+ * Synchronises. */
+pfn_status pfn_image_error(pfn_context *ctx, const float *dev_img, const float *dev_ref, int64_t n,
+                           double *host_rmse, double *host_rel_rmse, double *host_psnr);
+
+/* Tile shape of the ray-march launch: each wave covers tile_w x (64 / tile_w) pixels and a
+ * workgroup block_w x block_h waves (block_w * block_h = 4).  Chosen by the autotuner. */
+pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int block_h);
+
+/* ------------------------------------------------------------------ timing */
+/* When enabled, the main kernels are bracketed by HIP events on the stream they run on; the
+ * accumulated device time (ms) and launch count per kernel are returned by pfn_timing_get.
+ * kernel: 0 = ray march, 1 = photon trace, 2 = training step (fused forward/backward),
+ * 3 = path tracer, 4 = field query, 5 = Adam. */
+pfn_status pfn_timing_enable(pfn_context *ctx, int on);
+pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);
+pfn_status pfn_timing_reset(pfn_context *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFN_H */

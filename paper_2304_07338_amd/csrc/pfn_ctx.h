@@ -1,0 +1,132 @@
+// Host-side context of the library (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pfn.h"
+#include "march.h"
+#include "pfn_device.h"
+#include "pfn_field_dev.h"
+
+#define PFN_MAX_LIGHTS 4
+#define PFN_MAX_FIELDS 8
+
+struct FieldSlot {
+  bool init = false;
+  pfn_field_desc desc{};
+  GridLevels pos{}, dir{};
+  size_t pos_entries = 0, dir_entries = 0;  // table entries (2 features each)
+  size_t n_params = 0, mlp_off = 0;         // floats
+  size_t w_off[PFN_MAX_HIDDEN + 1] = {};    // float offset of each weight matrix
+  float *master = nullptr;                  // FP32 parameters
+  float *adam_m = nullptr, *adam_v = nullptr;
+  float *grad = nullptr;
+  uint32_t *lp_table[3] = {nullptr, nullptr, nullptr};  // packed 16-bit grid copies (f16, bf16)
+  void *mlp_packed[3] = {nullptr, nullptr, nullptr};    // LDS images per precision
+  bool lp_valid[3] = {false, false, false};
+  int64_t adam_t = 0;
+  double kappa = 1.0;
+};
+
+struct TileConfig {
+  int tile_w = 8, tile_h = 8, block_w = 2, block_h = 2;
+};
+
+struct pfn_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;
+  std::string err;
+
+  // scene
+  void *vol = nullptr;
+  pfn_dtype vol_dtype = PFN_F32;
+  BrickGrid vol_grid{};
+  size_t vol_elems = 0;
+  int nmax = 0;
+  float4 *tf_dev = nullptr;
+  float tf_host[1024] = {};
+  float ext_scale = 0.0f;
+  bool tf_set = false;
+  float majorant = 0.0f;
+  pfn_point_light lights[PFN_MAX_LIGHTS] = {};
+  int n_lights = 0;
+
+  // light-transmittance volume: 4 x f16 per texel (one channel per light)
+  ushort4 *lightvol = nullptr;
+  BrickGrid lv_grid{};
+  size_t lv_elems = 0;
+  bool lv_valid = false;
+
+  // photon cache: float4 (RGB, pad) per cell, [bins][res^3] x fastest
+  float4 *cache = nullptr;
+  int cache_bins = 0, cache_res = 0;
+  float g_bins[8] = {};
+  double kappa = 0.0;
+  bool cache_valid = false;
+
+  // photon records of the last trace (SoA) and their count
+  // photon records of the last trace: fixed slots photon * (max_collisions - 1) + k
+  float *rec_x = nullptr, *rec_w = nullptr, *rec_p = nullptr;
+  int32_t *rec_bin = nullptr;
+  uint8_t *rec_cnt = nullptr;   // records per photon
+  uint64_t rec_cap = 0, cnt_cap = 0, rec_count = 0, rec_photons = 0;
+  int rec_maxrec = 0;
+
+  FieldSlot fields[PFN_MAX_FIELDS];
+  int cur_field = 0;
+
+  // render launch state
+  MarchJob *jobs_dev = nullptr;
+  size_t jobs_cap = 0;
+  FieldDev *fields_dev = nullptr;
+  void **mlp_ptrs_dev = nullptr;
+  TileConfig tile;
+
+  // scratch for reductions and counters
+  void *scratch = nullptr;
+  size_t scratch_bytes = 0;
+
+  // timing
+  bool timing = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  double t_ms[8] = {};
+  int64_t t_n[8] = {};
+};
+
+enum TimedKernel { TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5 };
+
+// Error helpers
+pfn_status pfn_fail(pfn_context *ctx, pfn_status st, const std::string &msg);
+pfn_status pfn_hip(pfn_context *ctx, hipError_t e, const char *what);
+#define PFN_HIP(ctx, call)                                     \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return pfn_hip((ctx), e_, #call);    \
+  } while (0)
+
+pfn_status ensure_scratch(pfn_context *ctx, size_t bytes);
+void timing_begin(pfn_context *ctx);
+void timing_end(pfn_context *ctx, int kernel);
+
+// Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
+hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
+                               int nz);
+hipError_t launch_light_volume(pfn_context *ctx, float step);
+hipError_t launch_field_pack(pfn_context *ctx, FieldSlot &f, int prec);
+hipError_t launch_field_init(pfn_context *ctx, FieldSlot &f, uint64_t seed);
+hipError_t launch_field_query(pfn_context *ctx, const FieldSlot &f, int prec, const float *xyz,
+                              const float *dir, const float *g, int64_t n, float *lp, float *rgb);
+FieldDev make_field_dev(const FieldSlot &f, int prec);
+pfn_status field_refresh(pfn_context *ctx, FieldSlot &f, int prec);
+void field_params_changed(FieldSlot &f);
+pfn_status alloc_cache(pfn_context *ctx, int n_bins, int res);
+pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc);
+hipError_t launch_cache_pack(pfn_context *ctx, const float *src, size_t cells);
+hipError_t launch_cache_unpack(pfn_context *ctx, float *dst, size_t cells);
+pfn_status count_records(pfn_context *ctx, uint64_t *out);

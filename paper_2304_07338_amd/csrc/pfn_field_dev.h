@@ -1,0 +1,338 @@
+// Photon field on gfx950: multi-resolution grid encodings (position 3-D, direction 2-D, g raw)
+// and the ReLU MLP on the matrix cores, as device functions shared by the query, render and
+// training kernels.
+//
+// Matrix-core layout.  A 16-query tile is one wave: the MLP runs transposed, out^T = W * in^T,
+// with v_mfma_f32_16x16x32_{f16,bf16} (or 16x16x4 f32).  The accumulator of one 16x16 tile
+// holds, in lane l, rows 4*(l/16)+r (r = 0..3) of column l%16, which is exactly the shape of the
+// B operand of the next layer (k rows 8*(l/16)+i, column l%16) once two accumulator tiles are
+// concatenated.  The K order that this induces is a fixed permutation of the neurons, and the
+// same permutation is applied to the weights when they are packed into LDS, so activations
+// never leave registers between layers.  The input layer's B operand is produced directly by
+// the encoder: lane group q = l/16 computes grid levels 4q..4q+3 of query l%16.
+#pragma once
+#include "pfn_device.h"
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum Prec : int { P_F32 = 0, P_F16 = 1, P_BF16 = 2 };
+
+#define PFN_MAX_LEVELS 16
+#define PFN_MAX_HIDDEN 7
+#define PFN_WIDTH 64
+
+// Per-level constants of one grid encoding.
+struct GridLevels {
+  int res[PFN_MAX_LEVELS];
+  uint32_t off[PFN_MAX_LEVELS];  // entry offset of the level inside its table
+  uint32_t dense_mask;           // bit l: level l is a dense (unhashed) grid
+};
+
+struct FieldDev {
+  GridLevels pos, dir;
+  const void *pos_table;  // f32: float2 per entry; f16/bf16: 2 packed 16-bit features per entry
+  const void *dir_table;
+  uint32_t hash_mask;     // 2^log2_table - 1
+  int levels;
+  int hidden;             // hidden layers
+  float psi, kappa;
+};
+
+// Sizes (in elements) of the packed MLP image in LDS order.
+__host__ __device__ constexpr int mlp_packed_elems(int prec, int hidden) {
+  return prec == P_F32 ? (4 * 17 * 64 + (hidden - 1) * 4 * 16 * 64 + 16 * 64)
+                       : (4 * 3 * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 2 * 64 * 8);
+}
+
+// ------------------------------------------------------------------ encoding
+// The spatial hash of Mueller et al. (2022), Section 3: XOR of coordinate * prime.
+__device__ __forceinline__ uint32_t hash3(uint32_t x, uint32_t y, uint32_t z) {
+  return x ^ (y * 2654435761u) ^ (z * 805459861u);
+}
+__device__ __forceinline__ uint32_t hash2(uint32_t x, uint32_t y) { return x ^ (y * 2654435761u); }
+
+// Cell index and fraction of x in [0,1] on a level of resolution N: c = min(floor(xN), N-1),
+// f = xN - c computed with one rounding (fma) so that fine levels keep full precision.
+__device__ __forceinline__ void level_cell(float x, int N, int &c, float &f) {
+  float y = x * (float)N;
+  float fl = fminf(floorf(y), (float)(N - 1));
+  c = (int)fl;
+  f = fmaf(x, (float)N, -fl);
+}
+
+template <int P>
+__device__ __forceinline__ float2 load_feat(const void *table, uint32_t e) {
+  if constexpr (P == P_F32) {
+    return reinterpret_cast<const float2 *>(table)[e];
+  } else {
+    uint32_t v = reinterpret_cast<const uint32_t *>(table)[e];
+    if constexpr (P == P_F16) {
+      __half2 h = *reinterpret_cast<__half2 *>(&v);
+      return __half22float2(h);
+    } else {
+      return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xFFFF0000u));
+    }
+  }
+}
+
+// Level `lv` of the position grid at x: 2 interpolated features.
+template <int P>
+__device__ __forceinline__ float2 encode_pos_level(const FieldDev &F, int lv, f3 x) {
+  int N = F.pos.res[lv];
+  uint32_t off = F.pos.off[lv];
+  bool dense = (F.pos.dense_mask >> lv) & 1u;
+  int cx, cy, cz;
+  float fx, fy, fz;
+  level_cell(x.x, N, cx, fx);
+  level_cell(x.y, N, cy, fy);
+  level_cell(x.z, N, cz, fz);
+  float2 acc = make_float2(0.0f, 0.0f);
+  uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1)),
+             vz = (uint32_t)(cz + ((k >> 2) & 1));
+    uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+    float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy) *
+              (((k >> 2) & 1) ? fz : 1.0f - fz);
+    float2 v = load_feat<P>(F.pos_table, off + idx);
+    acc.x = fmaf(w, v.x, acc.x);
+    acc.y = fmaf(w, v.y, acc.y);
+  }
+  return acc;
+}
+
+// Cell and fraction on a direction level from a double-precision coordinate: the finest levels
+// have N ~ 7000 cells, so the coordinate is kept in FP64 until the fraction is formed.
+__device__ __forceinline__ void level_cell_d(double u, int N, int &c, float &f) {
+  double y = u * (double)N;
+  double fl = fmin(floor(y), (double)(N - 1));
+  c = (int)fl;
+  f = (float)(y - fl);
+}
+
+template <int P>
+__device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, double u0, double u1) {
+  int N = F.dir.res[lv];
+  uint32_t off = F.dir.off[lv];
+  bool dense = (F.dir.dense_mask >> lv) & 1u;
+  int cx, cy;
+  float fx, fy;
+  level_cell_d(u0, N, cx, fx);
+  level_cell_d(u1, N, cy, fy);
+  float2 acc = make_float2(0.0f, 0.0f);
+  uint32_t s1 = (uint32_t)(N + 1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1));
+    uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+    float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy);
+    float2 v = load_feat<P>(F.dir_table, off + idx);
+    acc.x = fmaf(w, v.x, acc.x);
+    acc.y = fmaf(w, v.y, acc.y);
+  }
+  return acc;
+}
+
+// Normalised spherical coordinates (theta/pi, (phi+pi)/(2pi)) of a unit direction, in FP64
+// (one evaluation per query; FP32 acos/atan2 rounding would be magnified by the fine levels).
+__device__ __forceinline__ void dir_coords(f3 w, double &u0, double &u1) {
+  const double pi = 3.14159265358979323846;
+  double z = fmin(1.0, fmax(-1.0, (double)w.z));
+  u0 = fmin(1.0, fmax(0.0, acos(z) / pi));
+  u1 = fmin(1.0, fmax(0.0, (atan2((double)w.y, (double)w.x) + pi) / (2.0 * pi)));
+}
+
+__device__ __forceinline__ f3 clamp01(f3 x) {
+  return {fminf(1.0f, fmaxf(0.0f, x.x)), fminf(1.0f, fmaxf(0.0f, x.y)),
+          fminf(1.0f, fmaxf(0.0f, x.z))};
+}
+
+// The 16 encoder outputs of this lane for one query: pos[0..7] = position levels 4q..4q+3
+// (2 features each), dir[0..7] = direction levels 4q..4q+3.  Levels >= F.levels give 0.
+template <int P>
+__device__ __forceinline__ void encode_lane(const FieldDev &F, int q, f3 x, double u0, double u1,
+                                            bool valid, float pos[8], float dir[8]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    int lv = 4 * q + j;
+    float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
+    if (valid && lv < F.levels) {
+      a = encode_pos_level<P>(F, lv, x);
+      b = encode_dir_level<P>(F, lv, u0, u1);
+    }
+    pos[2 * j] = a.x;
+    pos[2 * j + 1] = a.y;
+    dir[2 * j] = b.x;
+    dir[2 * j + 1] = b.y;
+  }
+}
+
+// ------------------------------------------------------------------ matrix-core MLP
+template <int P>
+struct Mma;
+
+template <>
+struct Mma<P_F16> {
+  typedef half8 vec;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec pack(const float *v) {
+    vec r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (_Float16)v[i];
+    return r;
+  }
+};
+
+template <>
+struct Mma<P_BF16> {
+  typedef bf16x8 vec;
+  static __device__ __forceinline__ f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ vec pack(const float *v) {
+    vec r;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) r[i] = (__bf16)v[i];
+    return r;
+  }
+};
+
+__device__ __forceinline__ f32x4 relu4(f32x4 v) {
+  return f32x4{fmaxf(v[0], 0.0f), fmaxf(v[1], 0.0f), fmaxf(v[2], 0.0f), fmaxf(v[3], 0.0f)};
+}
+
+// Forward pass of one 16-query tile at 16-bit precision.  w: packed weights in LDS (vec units);
+// b0 = position features, b1 = direction features, b2 = (g, 0, ...) for lane group 0.
+// Returns the output tile: lanes 0..15 hold (L'_r, L'_g, L'_b, 0) of query l.
+template <int P>
+__device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__restrict__ w,
+                                               int hidden, typename Mma<P>::vec b0,
+                                               typename Mma<P>::vec b1, typename Mma<P>::vec b2) {
+  typedef Mma<P> M;
+  typedef typename M::vec vec;
+  const int l = lane_id();
+  f32x4 acc[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+    a = M::mma(w[(mt * 3 + 0) * 64 + l], b0, a);
+    a = M::mma(w[(mt * 3 + 1) * 64 + l], b1, a);
+    a = M::mma(w[(mt * 3 + 2) * 64 + l], b2, a);
+    acc[mt] = relu4(a);
+  }
+  const vec *wl = w + 12 * 64;
+  for (int h = 1; h < hidden; ++h) {
+    float t0[8], t1[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      t0[r] = acc[0][r];
+      t0[4 + r] = acc[1][r];
+      t1[r] = acc[2][r];
+      t1[4 + r] = acc[3][r];
+    }
+    vec h0 = M::pack(t0), h1 = M::pack(t1);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+      a = M::mma(wl[(mt * 2 + 0) * 64 + l], h0, a);
+      a = M::mma(wl[(mt * 2 + 1) * 64 + l], h1, a);
+      acc[mt] = relu4(a);
+    }
+    wl += 8 * 64;
+  }
+  float t0[8], t1[8];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    t0[r] = acc[0][r];
+    t0[4 + r] = acc[1][r];
+    t1[r] = acc[2][r];
+    t1[4 + r] = acc[3][r];
+  }
+  vec h0 = M::pack(t0), h1 = M::pack(t1);
+  f32x4 out = {0.0f, 0.0f, 0.0f, 0.0f};
+  out = M::mma(wl[0 * 64 + l], h0, out);
+  out = M::mma(wl[1 * 64 + l], h1, out);
+  return out;
+}
+
+// FP32 variant on v_mfma_f32_16x16x4f32: one K=4 chunk per instruction; chunk c of the input
+// layer carries, in lane group q, position feature 8q+c (c < 8), direction feature 8q+c-8
+// (c < 16) or g (c = 16, q = 0); hidden chunk (t, r) carries neuron 16t+4q+r.
+__device__ __forceinline__ f32x4 mlp_forward16_f32(const float *__restrict__ w, int hidden,
+                                                   const float pos[8], const float dir[8],
+                                                   float gin) {
+  const int l = lane_id();
+  f32x4 acc[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float *wm = w + mt * 17 * 64 + l;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[c * 64], pos[c], a, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 + c) * 64], dir[c], a, 0, 0, 0);
+    a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * 64], gin, a, 0, 0, 0);
+    acc[mt] = relu4(a);
+  }
+  const float *wl = w + 4 * 17 * 64;
+  for (int h = 1; h < hidden; ++h) {
+    f32x4 nxt[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+      const float *wm = wl + mt * 16 * 64 + l;
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], acc[t][r], a, 0, 0, 0);
+      nxt[mt] = relu4(a);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt] = nxt[mt];
+    wl += 4 * 16 * 64;
+  }
+  f32x4 out = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      out = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[(t * 4 + r) * 64 + l], acc[t][r], out, 0, 0, 0);
+  return out;
+}
+
+// One 16-query tile: encode (lane group q computes levels 4q..4q+3 of query l%16) and run the
+// MLP.  Returns the output tile (lanes 0..15: L' of query l).
+template <int P>
+__device__ __forceinline__ f32x4 field_tile16(const FieldDev &F, const void *__restrict__ lds_w,
+                                              f3 x, double u0, double u1, float g, bool valid) {
+  const int q = lane_id() >> 4;
+  float pos[8], dir[8];
+  encode_lane<P>(F, q, clamp01(x), u0, u1, valid, pos, dir);
+  float gin = (q == 0) ? g : 0.0f;
+  if constexpr (P == P_F32) {
+    return mlp_forward16_f32(reinterpret_cast<const float *>(lds_w), F.hidden, pos, dir, gin);
+  } else {
+    typedef Mma<P> M;
+    float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+    return mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w), F.hidden,
+                            M::pack(pos), M::pack(dir), M::pack(gz));
+  }
+}
+
+// Copy the packed MLP image (global) into LDS with all threads of the block.
+__device__ __forceinline__ void stage_weights(void *lds, const void *__restrict__ src, int bytes) {
+  const int4 *s = reinterpret_cast<const int4 *>(src);
+  int4 *d = reinterpret_cast<int4 *>(lds);
+  for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) d[i] = s[i];
+}
+
+__device__ __forceinline__ float decode_lp(float lp, float psi, float kappa) {
+  return kappa * exp10f(-psi * lp);
+}

@@ -1,0 +1,100 @@
+// Scene volumes on the device: the density volume in 8^3-brick order, and the
+// light-transmittance grid (one f16 channel per light, half the volume resolution per axis).
+#include "pfn_ctx.h"
+
+template <typename T>
+__global__ void brick_kernel(const T *__restrict__ src, T *__restrict__ dst, BrickGrid g) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)g.nx * g.ny * g.nz;
+  if (i >= n) return;
+  int x = (int)(i % g.nx);
+  int y = (int)((i / g.nx) % g.ny);
+  int z = (int)(i / ((size_t)g.nx * g.ny));
+  dst[brick_ox(x) + brick_oy(g, y) + brick_oz(g, z)] = src[i];
+}
+
+hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
+                               int nz) {
+  size_t n = (size_t)nx * ny * nz;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (dt == PFN_F16)
+    hipLaunchKernelGGL(brick_kernel<__half>, dim3(blocks), dim3(256), 0, ctx->stream,
+                       (const __half *)src, (__half *)ctx->vol, ctx->vol_grid);
+  else
+    hipLaunchKernelGGL(brick_kernel<float>, dim3(blocks), dim3(256), 0, ctx->stream,
+                       (const float *)src, (float *)ctx->vol, ctx->vol_grid);
+  return hipGetLastError();
+}
+
+struct LightVolArgs {
+  const void *vol;
+  BrickGrid vg, lvg;
+  const float4 *tf;
+  float ext_scale, step;
+  int n_lights;
+  float lp[4][3];
+  ushort4 *out;
+};
+
+template <typename VT>
+__global__ void light_volume_kernel(LightVolArgs a) {
+  __shared__ float4 tf[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) tf[i] = a.tf[i];
+  __syncthreads();
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)a.lvg.nx * a.lvg.ny * a.lvg.nz;
+  if (i >= n) return;
+  int gx = (int)(i % a.lvg.nx);
+  int gy = (int)((i / a.lvg.nx) % a.lvg.ny);
+  int gz = (int)(i / ((size_t)a.lvg.nx * a.lvg.ny));
+  f3 x = {((float)gx + 0.5f) / (float)a.lvg.nx, ((float)gy + 0.5f) / (float)a.lvg.ny,
+          ((float)gz + 0.5f) / (float)a.lvg.nz};
+  float T[4] = {1.f, 1.f, 1.f, 1.f};
+  for (int l = 0; l < a.n_lights; ++l) {
+    f3 p = {a.lp[l][0], a.lp[l][1], a.lp[l][2]};
+    f3 v = p - x;
+    float dist = sqrtf(dot(v, v));
+    if (!(dist > 0.0f)) continue;
+    f3 d = v * (1.0f / dist);
+    float t0, t1;
+    if (!clip_cube(x, d, t0, t1)) continue;
+    float tend = fminf(t1, dist);
+    if (!(tend > t0)) continue;
+    float len = tend - t0, tau = 0.0f;
+    for (int k = 0;; ++k) {
+      float l_ = fminf(a.step, len - (float)k * a.step);
+      if (!(l_ > 0.0f)) break;
+      float t = t0 + (float)k * a.step + 0.5f * l_;
+      float rho = density_at(reinterpret_cast<const VT *>(a.vol), a.vg, x + d * t);
+      tau = fmaf(tf_lookup(tf, rho).w * a.ext_scale, l_, tau);
+    }
+    T[l] = expf(-tau);
+  }
+  ushort4 o;
+  o.x = __half_as_ushort(__float2half_rn(T[0]));
+  o.y = __half_as_ushort(__float2half_rn(T[1]));
+  o.z = __half_as_ushort(__float2half_rn(T[2]));
+  o.w = __half_as_ushort(__float2half_rn(T[3]));
+  a.out[brick_ox(gx) + brick_oy(a.lvg, gy) + brick_oz(a.lvg, gz)] = o;
+}
+
+hipError_t launch_light_volume(pfn_context *ctx, float step) {
+  LightVolArgs a{};
+  a.vol = ctx->vol;
+  a.vg = ctx->vol_grid;
+  a.lvg = ctx->lv_grid;
+  a.tf = ctx->tf_dev;
+  a.ext_scale = ctx->ext_scale;
+  a.step = step;
+  a.n_lights = ctx->n_lights;
+  for (int l = 0; l < ctx->n_lights; ++l)
+    for (int c = 0; c < 3; ++c) a.lp[l][c] = ctx->lights[l].pos[c];
+  a.out = ctx->lightvol;
+  size_t n = (size_t)a.lvg.nx * a.lvg.ny * a.lvg.nz;
+  unsigned blocks = (unsigned)((n + 255) / 256);
+  if (ctx->vol_dtype == PFN_F16)
+    hipLaunchKernelGGL(light_volume_kernel<__half>, dim3(blocks), dim3(256), 0, ctx->stream, a);
+  else
+    hipLaunchKernelGGL(light_volume_kernel<float>, dim3(blocks), dim3(256), 0, ctx->stream, a);
+  return hipGetLastError();
+}
