@@ -239,6 +239,11 @@ pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int bl
 pfn_status pfn_timing_enable(pfn_context *ctx, int on);
 pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);
 pfn_status pfn_timing_reset(pfn_context *ctx);
+/* When enabled, each ray-march launch also counts its march steps and its indirect-light
+ * queries (field evaluations with non-zero weight, or cache gathers); the counts of the last
+ * launch are returned by pfn_count_get.  Counting adds atomics and a synchronisation. */
+pfn_status pfn_count_enable(pfn_context *ctx, int on);
+pfn_status pfn_count_get(pfn_context *ctx, uint64_t *host_steps, uint64_t *host_queries);
 
 #ifdef __cplusplus
 }

@@ -103,6 +103,32 @@ void orc_hg_sample_dir(double g, const double w[3], double u1, double u2, double
   orc_normalize(out);
 }
 
+/* Emission from a point light p: uniform over the cone around the direction to the cube centre
+ * that just contains the cube's bounding sphere (radius sqrt(3)/2), or over the whole sphere
+ * when the light lies inside that sphere.  Returns the solid-angle fraction of the emitted
+ * directions (1 for the whole sphere), which scales the photon power so that the estimate stays
+ * unbiased: directions outside the cone cannot reach the cube. */
+double orc_emit_dir(const double p[3], double u1, double u2, double out[3]) {
+  double c[3] = {0.5 - p[0], 0.5 - p[1], 0.5 - p[2]};
+  double d = sqrt(orc_dot(c, c));
+  const double R = 0.5 * sqrt(3.0);
+  if (!(d > R)) {
+    orc_iso_dir(u1, u2, out);
+    return 1.0;
+  }
+  double axis[3] = {c[0] / d, c[1] / d, c[2] / d};
+  double cos_a = sqrt(1.0 - (R / d) * (R / d));
+  double ct = 1.0 - u1 * (1.0 - cos_a);
+  double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  double phi = 2.0 * M_PI * u2;
+  double t1[3], t2[3];
+  onb(axis, t1, t2);
+  double cp = cos(phi), sp = sin(phi);
+  for (int a = 0; a < 3; ++a) out[a] = ct * axis[a] + st * (cp * t1[a] + sp * t2[a]);
+  orc_normalize(out);
+  return 0.5 * (1.0 - cos_a);
+}
+
 void orc_iso_dir(double u1, double u2, double out[3]) {
   double z = 1.0 - 2.0 * u1;
   double r = sqrt(fmax(0.0, 1.0 - z * z));

@@ -65,6 +65,9 @@ double orc_exit_distance(const double x[3], const double d[3]);
 void orc_cell_corners(const double x[3], const int n[3], int i0[3], int i1[3], double f[3]);
 /* Isotropic direction from two uniforms: z = 1 - 2 u1, phi = 2 pi u2. */
 void orc_iso_dir(double u1, double u2, double out[3]);
+/* Photon emission direction from a point light (cone toward the cube); returns the fraction
+ * of the full sphere of directions that the cone covers. */
+double orc_emit_dir(const double p[3], double u1, double u2, double out[3]);
 /* Cache gather restricted to one bin. */
 void orc_cache_gather_bin(const orc_cache *c, int bin, const double x[3], double out[3]);
 #endif

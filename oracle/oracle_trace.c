@@ -6,8 +6,11 @@
  *  - photons are split equally over the lights and the phase pool (Section 4.4): photon `id`
  *    belongs to light id mod |L| and HG bin (id / |L|) mod |G|; its power is 4*pi*I divided by
  *    the number of photons of that (light, bin) pair;
- *  - emission is isotropic from the point light; free flights use delta tracking (Woodcock) with
- *    the global majorant ext_scale * max(A);
+ *  - emission from the point light is uniform over the cone of directions that contains the
+ *    cube's bounding sphere, with the photon power scaled by the cone's share of the sphere
+ *    (directions outside it never reach the volume, so this is the isotropic emission with the
+ *    certain misses removed); free flights use delta tracking (Woodcock) with the global
+ *    majorant ext_scale * max(A);
  *  - only interactions after the first are stored (Section 3.2), each with the power and
  *    direction with which the photon arrives there;
  *  - at a real collision the throughput is multiplied by the albedo (the opacity already sets
@@ -47,15 +50,14 @@ static int trace_one(const orc_scene *s, const orc_trace_params *p, double major
   uint64_t r = (uint64_t)l + (uint64_t)nL * (uint64_t)b;
   uint64_t n_lb = p->n_photons / groups + (r < p->n_photons % groups ? 1 : 0);
   const double *light = s->lights + 6 * l;
-  double phi0[3];
-  for (int c = 0; c < 3; ++c) phi0[c] = 4.0 * M_PI * light[3 + c] / (double)n_lb;
-  add3(st->emitted, phi0, 1.0);
-
   orc_rng rng;
   orc_rng_init(&rng, p->seed, id, ORC_STREAM_TRACE);
   double u1 = orc_rng_next(&rng), u2 = orc_rng_next(&rng);
   double dir[3];
-  orc_iso_dir(u1, u2, dir);
+  double frac = orc_emit_dir(light, u1, u2, dir);
+  double phi0[3];
+  for (int c = 0; c < 3; ++c) phi0[c] = 4.0 * M_PI * frac * light[3 + c] / (double)n_lb;
+  add3(st->emitted, phi0, 1.0);
   double o[3] = {light[0], light[1], light[2]};
   double t0, t1;
   if (!orc_clip_cube(o, dir, &t0, &t1)) {

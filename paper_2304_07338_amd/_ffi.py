@@ -106,6 +106,8 @@ SIGNATURES = {
     "pfn_timing_enable": (C.c_int, [ctxp, C.c_int]),
     "pfn_timing_get": (C.c_int, [ctxp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pfn_timing_reset": (C.c_int, [ctxp]),
+    "pfn_count_enable": (C.c_int, [ctxp, C.c_int]),
+    "pfn_count_get": (C.c_int, [ctxp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
 }
 
 _lib = None

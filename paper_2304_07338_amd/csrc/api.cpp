@@ -48,17 +48,39 @@ pfn_status ensure_scratch(pfn_context *ctx, size_t bytes) {
   return PFN_OK;
 }
 
+static void timing_collect(pfn_context *ctx) {
+  for (int i = 0; i < ctx->ev_pending; ++i) {
+    hipEvent_t a = ctx->ev_pool[2 * i], b = ctx->ev_pool[2 * i + 1];
+    if (hipEventSynchronize(b) != hipSuccess) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+      ctx->t_ms[ctx->ev_kernel[i]] += ms;
+      ctx->t_n[ctx->ev_kernel[i]] += 1;
+    }
+  }
+  ctx->ev_pending = 0;
+}
+
+// Event pair around one launch on the launch's stream; the host does not wait here.
 void timing_begin(pfn_context *ctx) {
-  if (ctx->timing) (void)hipEventRecord(ctx->ev0, ctx->stream);
+  if (!ctx->timing) return;
+  if (ctx->ev_pending >= 256) timing_collect(ctx);
+  int i = ctx->ev_pending;
+  while ((int)ctx->ev_pool.size() < 2 * (i + 1)) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    ctx->ev_pool.push_back(e);
+    ctx->ev_kernel.push_back(0);
+  }
+  (void)hipEventRecord(ctx->ev_pool[2 * i], ctx->stream);
 }
 void timing_end(pfn_context *ctx, int kernel) {
   if (!ctx->timing) return;
-  (void)hipEventRecord(ctx->ev1, ctx->stream);
-  (void)hipEventSynchronize(ctx->ev1);
-  float ms = 0.0f;
-  (void)hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1);
-  ctx->t_ms[kernel] += ms;
-  ctx->t_n[kernel] += 1;
+  int i = ctx->ev_pending;
+  if ((int)ctx->ev_pool.size() < 2 * (i + 1)) return;
+  (void)hipEventRecord(ctx->ev_pool[2 * i + 1], ctx->stream);
+  ctx->ev_kernel[i] = kernel;
+  ctx->ev_pending = i + 1;
 }
 
 static bool finite3(const float *v) {
@@ -85,10 +107,6 @@ extern "C" pfn_status pfn_create(int device, void *hip_stream, pfn_context **out
     }
     ctx->stream = ctx->own_stream;
   }
-  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
-    pfn_destroy(ctx);
-    return PFN_ERR_HIP;
-  }
   *out = ctx;
   return PFN_OK;
 }
@@ -101,7 +119,9 @@ static void free_field(FieldSlot &f) {
   for (int p = 0; p < 3; ++p) {
     dev_free(f.lp_table[p]);
     dev_free(f.mlp_packed[p]);
+    dev_free(f.mlp_bwd[p]);
     f.lp_valid[p] = false;
+    f.bwd_valid[p] = false;
   }
   f.init = false;
 }
@@ -121,11 +141,12 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   dev_free(ctx->rec_cnt);
   for (auto &f : ctx->fields) free_field(f);
   dev_free(ctx->scratch);
+  dev_free(ctx->train_act);
   dev_free(ctx->jobs_dev);
   dev_free(ctx->fields_dev);
   dev_free(ctx->mlp_ptrs_dev);
-  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
-  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  dev_free(ctx->counters);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
   delete ctx;
 }
@@ -406,7 +427,10 @@ pfn_status field_refresh(pfn_context *ctx, FieldSlot &f, int prec) {
 }
 
 void field_params_changed(FieldSlot &f) {
-  for (int p = 0; p < 3; ++p) f.lp_valid[p] = false;
+  for (int p = 0; p < 3; ++p) {
+    f.lp_valid[p] = false;
+    f.bwd_valid[p] = false;
+  }
 }
 
 extern "C" pfn_status pfn_field_num_params(pfn_context *ctx, size_t *n) {
@@ -457,7 +481,7 @@ extern "C" pfn_status pfn_field_query(pfn_context *ctx, pfn_dtype precision, con
                                       float *rgb) {
   CHECK_CTX(ctx);
   ARG(precision == PFN_F32 || precision == PFN_F16 || precision == PFN_BF16, "bad precision");
-  ARG(n >= 0 && n < ((int64_t)1 << 40), "n out of range");
+  ARG(n >= 0 && n < ((int64_t)1 << 38), "n out of range");
   ARG(n == 0 || (xyz && dir && g && lp), "NULL argument");
   pfn_status st = need_field(ctx, ctx->cur_field);
   if (st) return st;
@@ -650,9 +674,20 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
   a.tile_h = tc.tile_h;
   a.block_w = tc.block_w;
   a.block_h = tc.block_h;
+  a.counters = nullptr;
+  if (ctx->counting) {
+    if (!ctx->counters) PFN_HIP(ctx, dev_alloc((void **)&ctx->counters, 16));
+    PFN_HIP(ctx, hipMemsetAsync(ctx->counters, 0, 16, ctx->stream));
+    a.counters = ctx->counters;
+  }
   timing_begin(ctx);
   PFN_HIP(ctx, launch_march(a, ctx->vol_dtype, p0.direct, p0.indirect, prec, ctx->stream));
   timing_end(ctx, TK_MARCH);
+  if (ctx->counting) {
+    PFN_HIP(ctx, hipMemcpyAsync(ctx->last_counts, ctx->counters, 16, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   return PFN_OK;
 }
 
@@ -701,6 +736,7 @@ extern "C" pfn_status pfn_timing_enable(pfn_context *ctx, int on) {
 extern "C" pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *ms, int64_t *launches) {
   CHECK_CTX(ctx);
   ARG(kernel >= 0 && kernel < 8, "kernel id in [0, 8)");
+  timing_collect(ctx);
   if (ms) *ms = ctx->t_ms[kernel];
   if (launches) *launches = ctx->t_n[kernel];
   return PFN_OK;
@@ -708,6 +744,7 @@ extern "C" pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *ms, i
 
 extern "C" pfn_status pfn_timing_reset(pfn_context *ctx) {
   CHECK_CTX(ctx);
+  timing_collect(ctx);
   for (int i = 0; i < 8; ++i) {
     ctx->t_ms[i] = 0.0;
     ctx->t_n[i] = 0;
@@ -724,5 +761,18 @@ extern "C" pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int bloc
   ctx->tile.tile_h = 64 / tile_w;
   ctx->tile.block_w = block_w;
   ctx->tile.block_h = block_h;
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_count_enable(pfn_context *ctx, int on) {
+  CHECK_CTX(ctx);
+  ctx->counting = on != 0;
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_count_get(pfn_context *ctx, uint64_t *steps, uint64_t *queries) {
+  CHECK_CTX(ctx);
+  if (steps) *steps = ctx->last_counts[0];
+  if (queries) *queries = ctx->last_counts[1];
   return PFN_OK;
 }

@@ -148,6 +148,27 @@ __global__ void pack_mlp32_kernel(PackArgs a, float *out, int total) {
   out[idx] = v;
 }
 
+// Only the MLP image (used when the 16-bit grid copy has been refreshed elsewhere).
+hipError_t launch_field_pack_mlp(pfn_context *ctx, FieldSlot &f, int prec) {
+  PackArgs a{};
+  for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
+  a.hidden = f.desc.hidden_layers;
+  a.levels = f.desc.levels;
+  a.n_in = 4 * f.desc.levels + 1;
+  int total = mlp_packed_elems(prec, a.hidden);
+  unsigned blocks = (unsigned)((total + 255) / 256);
+  if (prec == P_F32)
+    hipLaunchKernelGGL(pack_mlp32_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       (float *)f.mlp_packed[prec], total);
+  else if (prec == P_BF16)
+    hipLaunchKernelGGL(pack_mlp16_kernel<P_BF16>, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       f.mlp_packed[prec], total);
+  else
+    hipLaunchKernelGGL(pack_mlp16_kernel<P_F16>, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       f.mlp_packed[prec], total);
+  return hipGetLastError();
+}
+
 hipError_t launch_field_pack(pfn_context *ctx, FieldSlot &f, int prec) {
   PackArgs a{};
   for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
@@ -206,8 +227,8 @@ __global__ __launch_bounds__(QUERY_THREADS) void field_query_kernel(
   __syncthreads();
   const int lane = lane_id();
   const int64_t wave = (int64_t)blockIdx.x * (QUERY_THREADS / 64) + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * (QUERY_THREADS / 64);
-  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+  const int64_t base = wave * 64;  // one group of 64 queries per wave
+  if (base < n) {
 #pragma unroll 1
     for (int j = 0; j < 4; ++j) {
       int64_t qi = base + 16 * j + (lane & 15);
@@ -238,7 +259,6 @@ hipError_t launch_field_query(pfn_context *ctx, const FieldSlot &f, int prec, co
   FieldDev F = make_field_dev(f, prec);
   int bytes = mlp_packed_elems(prec, f.desc.hidden_layers) * (prec == P_F32 ? 4 : 2);
   int64_t blocks = (n + QUERY_THREADS - 1) / QUERY_THREADS;
-  if (blocks > 256 * 16) blocks = 256 * 16;
   if (blocks < 1) blocks = 1;
   if (prec == P_F32)
     hipLaunchKernelGGL(field_query_kernel<P_F32>, dim3((unsigned)blocks), dim3(QUERY_THREADS),

@@ -35,6 +35,7 @@ struct MarchArgs {
   const MarchJob *jobs;
   int n_jobs, total_blocks;
   int tile_w, tile_h, block_w, block_h;  // lanes per tile row/column, tiles per block row/column
+  unsigned long long *counters;          // optional: [0] march steps, [1] field/cache queries
 };
 
 hipError_t launch_march(const MarchArgs &a, pfn_dtype vol_dtype, int direct, int ind, int prec,

@@ -119,7 +119,7 @@ __device__ __forceinline__ f3 cache_gather(const MarchArgs &a, const MarchJob &j
 // Field evaluation for the 64 queries of a wave (one per lane); returns the decoded L_i of this
 // lane's own query.  Must be called by all 64 lanes.
 template <int P>
-__device__ f3 field_eval_wave(const FieldDev &F, const void *lds_w, f3 xq, double u0, double u1,
+__device__ f3 field_eval_wave(const FieldDev &F, const void *lds_w, f3 xq, float u0, float u1,
                               float g, bool valid) {
   const int lane = lane_id();
   const uint64_t vm = ballot(valid);
@@ -129,9 +129,9 @@ __device__ f3 field_eval_wave(const FieldDev &F, const void *lds_w, f3 xq, doubl
     if (((vm >> (16 * j)) & 0xFFFFull) == 0) continue;
     const int src = 16 * j + (lane & 15);
     f3 x = {__shfl(xq.x, src), __shfl(xq.y, src), __shfl(xq.z, src)};
-    double a0 = __shfl(u0, src), a1 = __shfl(u1, src);
+    float a0 = __shfl(u0, src), a1 = __shfl(u1, src);
     bool v = (vm >> src) & 1ull;
-    f32x4 out = field_tile16<P>(F, lds_w, x, a0, a1, g, v);
+    f32x4 out = field_tile16<P>(F, lds_w, x, (double)a0, (double)a1, g, v);
     float o0 = __shfl(out[0], lane & 15), o1 = __shfl(out[1], lane & 15),
           o2 = __shfl(out[2], lane & 15);
     if ((lane >> 4) == j) {
@@ -195,10 +195,10 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
   int s = 0;
   bool live = false;
   f3 d = {0.f, 0.f, 1.f}, wo = {0.f, 0.f, -1.f};
-  float t0 = 0.f, span = 0.f, xi = 0.5f, T = 1.0f;
-  double u0 = 0.0, u1 = 0.0;
+  float t0 = 0.f, span = 0.f, xi = 0.5f, T = 1.0f, u0 = 0.f, u1 = 0.f;
   int n = 0, j = 0;
   f3 q = {0.f, 0.f, 0.f};
+  unsigned n_steps = 0, n_queries = 0;
   const int group = (IND == PFN_INDIRECT_FIELD) ? job.stride : 0x7fffffff;
 
   for (;;) {
@@ -210,6 +210,10 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
         o[1] = C.y * job.inv_spp;
         o[2] = C.z * job.inv_spp;
         active = false;
+        if (a.counters) {
+          atomicAdd(&a.counters[0], (unsigned long long)n_steps);
+          atomicAdd(&a.counters[1], (unsigned long long)n_queries);
+        }
         break;
       }
       float jx = 0.5f, jy = 0.5f;
@@ -235,7 +239,7 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
       j = 0;
       T = 1.0f;
       Cs = {0.f, 0.f, 0.f};
-      if constexpr (IND == PFN_INDIRECT_FIELD) dir_coords(wo, u0, u1);
+      if constexpr (IND == PFN_INDIRECT_FIELD) dir_coords_f(wo, u0, u1);
       live = n > 0;
     }
     if constexpr (IND == PFN_INDIRECT_FIELD) {
@@ -265,8 +269,12 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
         f3 alb = {o.x, o.y, o.z};
         f3 Ld = direct_light<VT, DIRECT>(a, job, tf, x, wo);
         f3 wgt = alb * (T * alpha);
+        ++n_steps;
         if constexpr (IND == PFN_INDIRECT_CACHE) {
-          if (j % job.stride == 0) q = cache_gather(a, job, x);
+          if (j % job.stride == 0) {
+            q = cache_gather(a, job, x);
+            ++n_queries;
+          }
           Cs = Cs + mul(wgt, Ld + q);
         } else if constexpr (IND == PFN_INDIRECT_FIELD) {
           if (k == 0) xq = x;
@@ -285,6 +293,7 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
     }
     if constexpr (IND == PFN_INDIRECT_FIELD) {
       bool valid = live && (W.x != 0.f || W.y != 0.f || W.z != 0.f);
+      n_queries += valid ? 1u : 0u;
       if (ballot(valid) != 0) {
         f3 Li = field_eval_wave<P>(F, lds_w, xq, u0, u1, job.g, valid);
         Cs = Cs + mul(W, Li);

@@ -29,6 +29,8 @@ struct FieldSlot {
   uint32_t *lp_table[3] = {nullptr, nullptr, nullptr};  // packed 16-bit grid copies (f16, bf16)
   void *mlp_packed[3] = {nullptr, nullptr, nullptr};    // LDS images per precision
   bool lp_valid[3] = {false, false, false};
+  void *mlp_bwd[3] = {nullptr, nullptr, nullptr};       // transposed images for training
+  bool bwd_valid[3] = {false, false, false};
   int64_t adam_t = 0;
   double kappa = 1.0;
 };
@@ -88,13 +90,24 @@ struct pfn_context {
   void **mlp_ptrs_dev = nullptr;
   TileConfig tile;
 
+  // training activations / deltas (neuron-major, 16-bit or FP32)
+  void *train_act = nullptr;
+  size_t train_act_bytes = 0;
+
   // scratch for reductions and counters
   void *scratch = nullptr;
   size_t scratch_bytes = 0;
 
-  // timing
+  // optional per-render counters (march steps, indirect queries)
+  bool counting = false;
+  unsigned long long *counters = nullptr;
+  unsigned long long last_counts[2] = {0, 0};
+
+  // timing: event pairs recorded around launches, collected when the totals are read
   bool timing = false;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> ev_pool;      // 2 events per slot
+  std::vector<int> ev_kernel;           // kernel id of each pending slot
+  int ev_pending = 0;
   double t_ms[8] = {};
   int64_t t_n[8] = {};
 };
@@ -119,6 +132,8 @@ hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, 
                                int nz);
 hipError_t launch_light_volume(pfn_context *ctx, float step);
 hipError_t launch_field_pack(pfn_context *ctx, FieldSlot &f, int prec);
+hipError_t launch_field_pack_mlp(pfn_context *ctx, FieldSlot &f, int prec);
+hipError_t launch_field_pack_bwd(pfn_context *ctx, FieldSlot &f, int prec);
 hipError_t launch_field_init(pfn_context *ctx, FieldSlot &f, uint64_t seed);
 hipError_t launch_field_query(pfn_context *ctx, const FieldSlot &f, int prec, const float *xyz,
                               const float *dir, const float *g, int64_t n, float *lp, float *rgb);

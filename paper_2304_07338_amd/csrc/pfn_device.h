@@ -48,12 +48,15 @@ struct Philox {
     c3 += 1u;
     pos = 0;
   }
-  // Uniform in (0,1): ((x >> 9) + 1/2) * 2^-23, exact in binary32.
-  __device__ __forceinline__ float next() {
+  __device__ __forceinline__ uint32_t next_u32() {
     if (pos == 4) block();
     uint32_t x = pos == 0 ? b0 : pos == 1 ? b1 : pos == 2 ? b2 : b3;
     ++pos;
-    return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f);
+    return x;
+  }
+  // Uniform in (0,1): ((x >> 9) + 1/2) * 2^-23, exact in binary32.
+  __device__ __forceinline__ float next() {
+    return ((float)(next_u32() >> 9) + 0.5f) * (1.0f / 8388608.0f);
   }
 };
 
@@ -103,6 +106,42 @@ __device__ __forceinline__ f3 hg_sample_dir(float g, f3 w, float u1, float u2) {
   sincosf(phi, &sp, &cp);
   f3 d = w * mu + (t1 * cp + t2 * sp) * s;
   return normalize3(d);
+}
+
+// Orthonormal basis around a unit vector (Duff et al., JCGT 2017).
+__device__ __forceinline__ void onb(f3 w, f3 &t1, f3 &t2) {
+  float sign = w.z >= 0.0f ? 1.0f : -1.0f;
+  float a = -1.0f / (sign + w.z);
+  float b = w.x * w.y * a;
+  t1 = {1.0f + sign * w.x * w.x * a, sign * b, -sign * w.x};
+  t2 = {b, sign + w.y * w.y * a, -w.y};
+}
+
+__device__ __forceinline__ f3 iso_dir(float u1, float u2);
+
+// Photon emission from a point light p: uniform over the cone around the direction to the cube
+// centre that contains the cube's bounding sphere (whole sphere if p is inside it).  Returns the
+// cone's share of the full sphere, which scales the photon power (directions outside the cone
+// cannot reach the cube).
+__device__ __forceinline__ float emit_dir(f3 p, float u1, float u2, f3 &out) {
+  f3 c = {0.5f - p.x, 0.5f - p.y, 0.5f - p.z};
+  float d = sqrtf(dot(c, c));
+  const float R = 0.86602540378443865f;
+  if (!(d > R)) {
+    out = iso_dir(u1, u2);
+    return 1.0f;
+  }
+  f3 axis = c * (1.0f / d);
+  float q = R / d;
+  float cos_a = sqrtf(1.0f - q * q);
+  float ct = 1.0f - u1 * (1.0f - cos_a);
+  float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  float sp, cp;
+  sincosf(2.0f * PFN_PI * u2, &sp, &cp);
+  f3 t1, t2;
+  onb(axis, t1, t2);
+  out = normalize3(axis * ct + (t1 * cp + t2 * sp) * st);
+  return 0.5f * (1.0f - cos_a);
 }
 
 __device__ __forceinline__ f3 iso_dir(float u1, float u2) {

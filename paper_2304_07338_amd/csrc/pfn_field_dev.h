@@ -145,6 +145,13 @@ __device__ __forceinline__ void dir_coords(f3 w, double &u0, double &u1) {
   u1 = fmin(1.0, fmax(0.0, (atan2((double)w.y, (double)w.x) + pi) / (2.0 * pi)));
 }
 
+// FP32 variant for the renderer, whose view directions are themselves FP32 ray directions.
+__device__ __forceinline__ void dir_coords_f(f3 w, float &u0, float &u1) {
+  float z = fminf(1.0f, fmaxf(-1.0f, w.z));
+  u0 = fminf(1.0f, fmaxf(0.0f, acosf(z) * (1.0f / PFN_PI)));
+  u1 = fminf(1.0f, fmaxf(0.0f, (atan2f(w.y, w.x) + PFN_PI) * (0.5f / PFN_PI)));
+}
+
 __device__ __forceinline__ f3 clamp01(f3 x) {
   return {fminf(1.0f, fmaxf(0.0f, x.x)), fminf(1.0f, fmaxf(0.0f, x.y)),
           fminf(1.0f, fmaxf(0.0f, x.z))};

@@ -1,9 +1,10 @@
 // Multi-phase photon tracing (Algorithm 1) and the isotropic per-bin photon cache.
 //
 // One lane per photon path.  Photon `id` belongs to light id mod |L| and HG bin (id/|L|) mod |G|
-// (photons split evenly over lights and phases, Section 4.4), is emitted isotropically from the
-// point light with power 4*pi*I / N(light, bin), and flies by delta tracking with the global
-// majorant.  At every real collision after the first it writes a record (position, incident
+// (photons split evenly over lights and phases, Section 4.4), leaves the point light in a
+// direction drawn uniformly from the cone that contains the cube (the isotropic emission with
+// the certain misses removed) with power 4*pi*I*share / N(light, bin), and flies by delta
+// tracking with the global majorant.  At every real collision after the first it writes a record (position, incident
 // direction, incident power, bin) into its own fixed slots, so records come out in photon order
 // without any cross-lane coordination; the throughput is multiplied by the albedo, the direction
 // is resampled from HG(g_bin), and Russian roulette may end the path.  Power tallies are kept in
@@ -38,18 +39,18 @@ __global__ __launch_bounds__(TRACE_THREADS) void trace_kernel(TraceArgs a) {
     const int b = (int)((id / (uint64_t)a.n_lights) % (uint64_t)a.n_bins);
     const uint64_t r = (uint64_t)l + (uint64_t)a.n_lights * (uint64_t)b;
     const uint64_t n_lb = a.n_photons / groups + (r < a.n_photons % groups ? 1 : 0);
-    const float s0 = (float)(4.0 * 3.14159265358979323846 / (double)n_lb);
+    const float g = a.g_bins[b];
+    Philox rng;
+    rng.init(a.seed, id, STREAM_TRACE);
+    float ua = rng.next(), ub = rng.next();
+    f3 o = {a.light_pos[l][0], a.light_pos[l][1], a.light_pos[l][2]};
+    f3 dir;
+    float frac = emit_dir(o, ua, ub, dir);
+    const float s0 = (float)(4.0 * 3.14159265358979323846 / (double)n_lb) * frac;
     f3 phi0 = {a.light_int[l][0] * s0, a.light_int[l][1] * s0, a.light_int[l][2] * s0};
     tal[0] += phi0.x;  // emitted
     tal[1] += phi0.y;
     tal[2] += phi0.z;
-    const float g = a.g_bins[b];
-
-    Philox rng;
-    rng.init(a.seed, id, STREAM_TRACE);
-    float ua = rng.next(), ub = rng.next();
-    f3 dir = iso_dir(ua, ub);
-    f3 o = {a.light_pos[l][0], a.light_pos[l][1], a.light_pos[l][2]};
     float t, tmax;
     int nrec = 0;
     if (!clip_cube(o, dir, t, tmax)) {

@@ -1,23 +1,953 @@
-// Field training (Section 3.5): batch generation, fused forward/backward, Adam.
+// Photon-field training (Section 3.5) on gfx950.
+//
+// One step = three kernels:
+//  1. train_fb_kernel: per 16-sample tile (one wave), draw the batch (Section 3.3: uniform x,
+//     uniform direction, g from the phase pool; target = Eq. (6) of the cache value / kappa),
+//     encode, run the MLP forward on the matrix cores with activations kept in registers, take
+//     the L2 residual, run the backward pass back to the encoder inputs with the transposed
+//     weight images, and scatter the encoder gradients into the FP32 grid gradients with
+//     atomics.  The per-sample layer inputs and output gradients are written out (16-bit,
+//     neuron-major) for the weight gradients.
+//  2. dw_kernel: the weight gradients dW = sum_n delta_n a_n^T as split-K matrix-core products
+//     over the batch, added atomically into the FP32 gradient.
+//  3. adam_kernel: bias-corrected Adam on the FP32 master parameters (every parameter, every
+//     step), refreshing the 16-bit grid copy in the same pass and clearing the gradient.
+// Gradients are formed from the unscaled residuals y - y* and scaled by 2 / (3 n) in Adam (the
+// derivative of the mean over n samples and 3 channels), which keeps 16-bit deltas in range.
 #include "pfn_ctx.h"
 
-extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *, float *) {
-  if (!ctx) return PFN_ERR_INVALID_ARG;
-  return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training not built yet");
+#define TRAIN_THREADS 256
+
+// ------------------------------------------------------------------ batch generation
+struct SampleSrc {
+  uint64_t seed;
+  int64_t step;
+  const float4 *cache;
+  int cache_res, n_bins;
+  float g_bins[8];
+  float inv_kappa, psi;
+};
+
+__device__ __forceinline__ float log_target(float v, float psi) {
+  // Eq. (6): -log10(v) / psi above the precision threshold 10^-psi, else 1
+  return v > exp10f(-psi) ? -log10f(v) / psi : 1.0f;
 }
-extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t, int64_t, int64_t, float *, float *,
-                                      float *, int32_t *, float *) {
-  if (!ctx) return PFN_ERR_INVALID_ARG;
-  return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training not built yet");
+
+__device__ __forceinline__ void gen_sample(const SampleSrc &s, int64_t i, f3 &x, f3 &w, float &g,
+                                           int &bin, float tgt[3]) {
+  Philox r;
+  r.init(s.seed, ((uint64_t)s.step << 32) | (uint64_t)(uint32_t)i, STREAM_TRAIN);
+  x.x = r.next();
+  x.y = r.next();
+  x.z = r.next();
+  // bin = floor(u * n_bins) with u = (k + 1/2) 2^-23, in exact integer arithmetic
+  uint32_t k = r.next_u32() >> 9;
+  bin = (int)(((2ull * k + 1ull) * (uint64_t)s.n_bins) >> 24);
+  float u1 = r.next(), u2 = r.next();
+  w = iso_dir(u1, u2);
+  g = s.g_bins[bin];
+  const int R = s.cache_res;
+  int i0, i1, j0, j1, k0, k1;
+  float fx, fy, fz;
+  tri_axis(x.x, R, i0, i1, fx);
+  tri_axis(x.y, R, j0, j1, fy);
+  tri_axis(x.z, R, k0, k1, fz);
+  const float4 *c = s.cache + (size_t)bin * R * R * R;
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    int ix = (q & 1) ? i1 : i0, iy = (q & 2) ? j1 : j0, iz = (q & 4) ? k1 : k0;
+    float wq = ((q & 1) ? fx : 1.0f - fx) * ((q & 2) ? fy : 1.0f - fy) * ((q & 4) ? fz : 1.0f - fz);
+    float4 e = c[((size_t)iz * R + iy) * R + ix];
+    v0 = fmaf(wq, e.x, v0);
+    v1 = fmaf(wq, e.y, v1);
+    v2 = fmaf(wq, e.z, v2);
+  }
+  tgt[0] = log_target(v0 * s.inv_kappa, s.psi);
+  tgt[1] = log_target(v1 * s.inv_kappa, s.psi);
+  tgt[2] = log_target(v2 * s.inv_kappa, s.psi);
 }
-extern "C" pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype, const float *,
-                                                 const float *, const float *, const float *,
-                                                 int64_t, double *, float *) {
-  if (!ctx) return PFN_ERR_INVALID_ARG;
-  return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training not built yet");
+
+__global__ void train_batch_kernel(SampleSrc s, int64_t n, float *xyz, float *dir, float *g,
+                                   int32_t *bin, float *tgt) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  f3 x, w;
+  float gg, t[3];
+  int b;
+  gen_sample(s, i, x, w, gg, b, t);
+  if (xyz) {
+    xyz[3 * i] = x.x;
+    xyz[3 * i + 1] = x.y;
+    xyz[3 * i + 2] = x.z;
+  }
+  if (dir) {
+    dir[3 * i] = w.x;
+    dir[3 * i + 1] = w.y;
+    dir[3 * i + 2] = w.z;
+  }
+  if (g) g[i] = gg;
+  if (bin) bin[i] = b;
+  if (tgt) {
+    tgt[3 * i] = t[0];
+    tgt[3 * i + 1] = t[1];
+    tgt[3 * i + 2] = t[2];
+  }
 }
-extern "C" pfn_status pfn_field_adam_step(pfn_context *ctx, const float *, int64_t, float, float,
-                                          float, float) {
+
+// ------------------------------------------------------------------ backward weight images
+// Transposed weights in matrix-core operand order:
+//  lastT  : dh = W_H^T e      (4 row tiles x 1 K chunk; K = the 3 output channels)
+//  hidT[k]: dh = W_k^T delta  (rows = inputs of W_k in natural order, K = outputs of W_k in the
+//                              order the delta tiles are packed)
+//  firstT : dz = W_0^T delta  (rows permuted so that lane group q receives the gradients of the
+//                              encoder features it computed: tile 0/1 = position features
+//                              8q..8q+7, tile 2/3 = direction features 8q..8q+7)
+struct BwdPackArgs {
+  const float *w[PFN_MAX_HIDDEN + 1];
+  int hidden, levels, n_in;
+};
+
+__host__ __device__ constexpr int bwd_elems(int prec, int hidden) {
+  return prec == P_F32 ? (4 * 64 + (hidden - 1) * 4 * 16 * 64 + 4 * 16 * 64)
+                       : (4 * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 4 * 2 * 64 * 8);
+}
+
+// Input column of W_0 whose gradient lands in row rho of row tile mt (-1: none).
+__device__ __forceinline__ int first_row_col(const BwdPackArgs &a, int mt, int rho) {
+  int qq = rho >> 2, r = rho & 3;
+  int feat = 8 * qq + ((mt & 1) ? 4 : 0) + r;  // feature slot of lane group qq
+  int lv = feat >> 1, f = feat & 1;
+  if (lv >= a.levels) return -1;
+  return (mt < 2 ? 0 : 2 * a.levels) + 2 * lv + f;
+}
+__device__ __forceinline__ int hid_col_b(int c, int q, int i) {
+  return i < 4 ? 32 * c + 4 * q + i : 32 * c + 16 + 4 * q + (i - 4);
+}
+
+template <int P>
+__global__ void pack_bwd16_kernel(BwdPackArgs a, void *out, int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int i = idx & 7, l = (idx >> 3) & 63, blk = idx >> 9;
+  int rho = l & 15, q = l >> 4;
+  float v = 0.0f;
+  const int H = a.hidden;
+  if (blk < 4) {  // lastT
+    int mt = blk;
+    if (q == 0 && i < 3) v = a.w[H][i * PFN_WIDTH + 16 * mt + rho];
+  } else if (blk < 4 + (H - 1) * 8) {  // hidT for layers 1..H-1
+    int rb = blk - 4;
+    int k = 1 + rb / 8, mt = (rb % 8) / 2, c = rb % 2;
+    v = a.w[k][hid_col_b(c, q, i) * PFN_WIDTH + 16 * mt + rho];
+  } else {  // firstT
+    int rb = blk - 4 - (H - 1) * 8;
+    int mt = rb / 2, c = rb % 2;
+    int col = first_row_col(a, mt, rho);
+    if (col >= 0) v = a.w[0][hid_col_b(c, q, i) * a.n_in + col];
+  }
+  if constexpr (P == P_F16) reinterpret_cast<_Float16 *>(out)[idx] = (_Float16)v;
+  else reinterpret_cast<__bf16 *>(out)[idx] = (__bf16)v;
+}
+
+__global__ void pack_bwd32_kernel(BwdPackArgs a, float *out, int total) {
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int l = idx & 63, blk = idx >> 6;
+  int rho = l & 15, q = l >> 4;
+  float v = 0.0f;
+  const int H = a.hidden;
+  if (blk < 4) {  // lastT: lane group q carries channel q
+    int mt = blk;
+    if (q < 3) v = a.w[H][q * PFN_WIDTH + 16 * mt + rho];
+  } else if (blk < 4 + (H - 1) * 64) {
+    int rb = blk - 4;
+    int k = 1 + rb / 64, mt = (rb % 64) / 16, tr = rb % 16;
+    int t = tr >> 2, r = tr & 3;
+    v = a.w[k][(16 * t + 4 * q + r) * PFN_WIDTH + 16 * mt + rho];
+  } else {
+    int rb = blk - 4 - (H - 1) * 64;
+    int mt = rb / 16, tr = rb % 16;
+    int t = tr >> 2, r = tr & 3;
+    int col = first_row_col(a, mt, rho);
+    if (col >= 0) v = a.w[0][(16 * t + 4 * q + r) * a.n_in + col];
+  }
+  out[idx] = v;
+}
+
+hipError_t launch_field_pack_bwd(pfn_context *ctx, FieldSlot &f, int prec) {
+  BwdPackArgs a{};
+  for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
+  a.hidden = f.desc.hidden_layers;
+  a.levels = f.desc.levels;
+  a.n_in = 4 * f.desc.levels + 1;
+  int total = bwd_elems(prec, a.hidden);
+  unsigned blocks = (unsigned)((total + 255) / 256);
+  if (prec == P_F32)
+    hipLaunchKernelGGL(pack_bwd32_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       (float *)f.mlp_bwd[prec], total);
+  else if (prec == P_BF16)
+    hipLaunchKernelGGL(pack_bwd16_kernel<P_BF16>, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       f.mlp_bwd[prec], total);
+  else
+    hipLaunchKernelGGL(pack_bwd16_kernel<P_F16>, dim3(blocks), dim3(256), 0, ctx->stream, a,
+                       f.mlp_bwd[prec], total);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fused forward/backward
+struct TrainArgs {
+  FieldDev F;
+  const void *fwd;  // packed forward weights (operand order)
+  const void *bwd;  // packed transposed weights
+  SampleSrc src;
+  const float *in_xyz, *in_dir, *in_g, *in_tgt;  // used when samples are given
+  int64_t n, ldn;   // samples, padded leading dimension (multiple of 32)
+  float *grad_pos, *grad_dir;  // FP32 gradients of the grid tables (2 floats per entry)
+  void *act;        // per-layer deltas and inputs, neuron-major [rows][ldn]
+  int64_t delta_off[PFN_MAX_HIDDEN + 1], in_off[PFN_MAX_HIDDEN + 1];  // element offsets
+  double *loss;     // accumulated sum of squared residuals
+};
+
+template <typename T>
+__device__ __forceinline__ T to_t(float v);
+template <>
+__device__ __forceinline__ _Float16 to_t<_Float16>(float v) {
+  return (_Float16)v;
+}
+template <>
+__device__ __forceinline__ __bf16 to_t<__bf16>(float v) {
+  return (__bf16)v;
+}
+template <>
+__device__ __forceinline__ float to_t<float>(float v) {
+  return v;
+}
+
+template <int P>
+struct ActT {
+  typedef _Float16 type;
+};
+template <>
+struct ActT<P_BF16> {
+  typedef __bf16 type;
+};
+template <>
+struct ActT<P_F32> {
+  typedef float type;
+};
+
+// Scatter the encoder-input gradients of this lane's 4 levels into the grid gradients.
+__device__ __forceinline__ void scatter_grid_grads(const TrainArgs &a, int q, f3 x, double u0,
+                                                   double u1, const float gp[8], const float gd[8]) {
+  const FieldDev &F = a.F;
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    int lv = 4 * q + j;
+    if (lv >= F.levels) break;
+    {
+      int N = F.pos.res[lv];
+      uint32_t off = F.pos.off[lv];
+      bool dense = (F.pos.dense_mask >> lv) & 1u;
+      int cx, cy, cz;
+      float fx, fy, fz;
+      level_cell(x.x, N, cx, fx);
+      level_cell(x.y, N, cy, fy);
+      level_cell(x.z, N, cz, fz);
+      uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1)),
+                 vz = (uint32_t)(cz + ((k >> 2) & 1));
+        uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+        float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy) *
+                  (((k >> 2) & 1) ? fz : 1.0f - fz);
+        float *e = a.grad_pos + 2 * (size_t)(off + idx);
+        atomicAdd(e, w * gp[2 * j]);
+        atomicAdd(e + 1, w * gp[2 * j + 1]);
+      }
+    }
+    {
+      int N = F.dir.res[lv];
+      uint32_t off = F.dir.off[lv];
+      bool dense = (F.dir.dense_mask >> lv) & 1u;
+      int cx, cy;
+      float fx, fy;
+      level_cell_d(u0, N, cx, fx);
+      level_cell_d(u1, N, cy, fy);
+      uint32_t s1 = (uint32_t)(N + 1);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1));
+        uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+        float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy);
+        float *e = a.grad_dir + 2 * (size_t)(off + idx);
+        atomicAdd(e, w * gd[2 * j]);
+        atomicAdd(e + 1, w * gd[2 * j + 1]);
+      }
+    }
+  }
+}
+
+template <int P, int H, bool GEN>
+__global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
+  typedef typename ActT<P>::type T;
+  // One 16-sample tile per wave and no loop over tiles: the weight operands are then not
+  // loop-invariant, so the compiler streams them from cache instead of pinning them in registers.
+  const int lane = lane_id(), q = lane >> 4, nl = lane & 15;
+  const int64_t tile = (int64_t)blockIdx.x * (TRAIN_THREADS / 64) + (threadIdx.x >> 6);
+  const int64_t ntiles = a.ldn / 16;
+  const int L = a.F.levels;
+  T *act = reinterpret_cast<T *>(a.act);
+  double wave_loss = 0.0;
+  if (tile < ntiles) {
+    const int64_t i = tile * 16 + nl;
+    const bool valid = i < a.n;
+    f3 x = {0.f, 0.f, 0.f}, w = {0.f, 0.f, 1.f};
+    float g = 0.f, tgt[3] = {0.f, 0.f, 0.f};
+    if (valid) {
+      if constexpr (GEN) {
+        int b;
+        gen_sample(a.src, i, x, w, g, b, tgt);
+      } else {
+        x = {a.in_xyz[3 * i], a.in_xyz[3 * i + 1], a.in_xyz[3 * i + 2]};
+        w = {a.in_dir[3 * i], a.in_dir[3 * i + 1], a.in_dir[3 * i + 2]};
+        g = a.in_g[i];
+        tgt[0] = a.in_tgt[3 * i];
+        tgt[1] = a.in_tgt[3 * i + 1];
+        tgt[2] = a.in_tgt[3 * i + 2];
+      }
+    }
+    x = clamp01(x);
+    double u0, u1;
+    dir_coords(w, u0, u1);
+    float pos[8], dir[8];
+    encode_lane<P>(a.F, q, x, u0, u1, valid, pos, dir);
+    const float gin = (q == 0) ? g : 0.0f;
+
+    // layer-0 inputs (rows = network input index)
+    {
+      T *in0 = act + a.in_off[0];
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        int lv = 4 * q + (s >> 1);
+        if (lv < L) {
+          in0[(int64_t)(2 * lv + (s & 1)) * a.ldn + i] = to_t<T>(valid ? pos[s] : 0.f);
+          in0[(int64_t)(2 * L + 2 * lv + (s & 1)) * a.ldn + i] = to_t<T>(valid ? dir[s] : 0.f);
+        }
+      }
+      if (q == 0) in0[(int64_t)(4 * L) * a.ldn + i] = to_t<T>(valid ? g : 0.f);
+    }
+
+    float e[3];
+    if constexpr (P == P_F32) {
+      const float *W = reinterpret_cast<const float *>(a.fwd);
+      const float *B = reinterpret_cast<const float *>(a.bwd);
+      f32x4 hv[H][4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        const float *wm = W + mt * 17 * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[k * 64], pos[k], c, 0, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 + k) * 64], dir[k], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * 64], gin, c, 0, 0, 0);
+        hv[0][mt] = relu4(c);
+      }
+      const float *wl = W + 4 * 17 * 64;
+#pragma unroll
+      for (int k = 1; k < H; ++k) {
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          f32x4 c = {0.f, 0.f, 0.f, 0.f};
+          const float *wm = wl + mt * 16 * 64 + lane;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], hv[k - 1][t][r], c, 0, 0, 0);
+          hv[k][mt] = relu4(c);
+        }
+        wl += 4 * 16 * 64;
+      }
+      f32x4 out = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[(t * 4 + r) * 64 + lane], hv[H - 1][t][r], out, 0, 0, 0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[c] = valid ? (__shfl(out[c], nl) - tgt[c]) : 0.0f;
+      // output layer: delta = e (rows = channels), input = h_{H-1}
+      if (q == 0) {
+        T *d = act + a.delta_off[H];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[(int64_t)c * a.ldn + i] = to_t<T>(e[c]);
+      }
+      f32x4 acc[4];
+      const float ec = q < 3 ? e[q] : 0.0f;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(B[mt * 64 + lane], ec, c, 0, 0, 0);
+      }
+      const float *bh = B + 4 * 64;
+#pragma unroll
+      for (int k = H - 1; k >= 0; --k) {
+        // inputs of layer k+1 (= h_k) and the output gradient of layer k
+        T *ik = act + a.in_off[k + 1];
+        T *dk = act + a.delta_off[k];
+        T *ib = ik + (int64_t)(4 * q) * a.ldn + i;
+        T *db = dk + (int64_t)(4 * q) * a.ldn + i;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t ro = (int64_t)(16 * t + r) * a.ldn;  // row 16t + 4q + r
+            float h = hv[k][t][r];
+            acc[t][r] = h > 0.0f ? acc[t][r] : 0.0f;
+            ib[ro] = to_t<T>(h);
+            db[ro] = to_t<T>(acc[t][r]);
+          }
+        const float *img = (k >= 1) ? bh + (k - 1) * 4 * 16 * 64 : bh + (H - 1) * 4 * 16 * 64;
+        f32x4 nxt[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          f32x4 c = {0.f, 0.f, 0.f, 0.f};
+          const float *wm = img + mt * 16 * 64 + lane;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], acc[t][r], c, 0, 0, 0);
+          nxt[mt] = c;
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = nxt[mt];
+      }
+      if (valid) {
+        float gp[8], gd[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          gp[r] = acc[0][r];
+          gp[4 + r] = acc[1][r];
+          gd[r] = acc[2][r];
+          gd[4 + r] = acc[3][r];
+        }
+        scatter_grid_grads(a, q, x, u0, u1, gp, gd);
+      }
+    } else {
+      typedef Mma<P> M;
+      typedef typename M::vec vec;
+      const vec *W = reinterpret_cast<const vec *>(a.fwd);
+      const vec *B = reinterpret_cast<const vec *>(a.bwd);
+      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+      vec b0 = M::pack(pos), b1 = M::pack(dir), b2 = M::pack(gz);
+      vec hv[H][2];
+      f32x4 acc[4];
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        c = M::mma(W[(mt * 3 + 0) * 64 + lane], b0, c);
+        c = M::mma(W[(mt * 3 + 1) * 64 + lane], b1, c);
+        c = M::mma(W[(mt * 3 + 2) * 64 + lane], b2, c);
+        acc[mt] = relu4(c);
+      }
+      const vec *wl = W + 12 * 64;
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        float t0[8], t1[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          t0[r] = acc[0][r];
+          t0[4 + r] = acc[1][r];
+          t1[r] = acc[2][r];
+          t1[4 + r] = acc[3][r];
+        }
+        hv[k][0] = M::pack(t0);
+        hv[k][1] = M::pack(t1);
+        if (k + 1 < H) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            c = M::mma(wl[(mt * 2 + 0) * 64 + lane], hv[k][0], c);
+            c = M::mma(wl[(mt * 2 + 1) * 64 + lane], hv[k][1], c);
+            acc[mt] = relu4(c);
+          }
+          wl += 8 * 64;
+        }
+      }
+      f32x4 out = {0.f, 0.f, 0.f, 0.f};
+      out = M::mma(wl[0 * 64 + lane], hv[H - 1][0], out);
+      out = M::mma(wl[1 * 64 + lane], hv[H - 1][1], out);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) e[c] = valid ? (__shfl(out[c], nl) - tgt[c]) : 0.0f;
+      if (q == 0) {
+        T *d = act + a.delta_off[H];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[(int64_t)c * a.ldn + i] = to_t<T>(e[c]);
+      }
+      float ev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (q == 0) {
+        ev[0] = e[0];
+        ev[1] = e[1];
+        ev[2] = e[2];
+      }
+      vec be = M::pack(ev);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) {
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        acc[mt] = M::mma(B[mt * 64 + lane], be, c);
+      }
+      const vec *bh = B + 4 * 64;
+#pragma unroll
+      for (int k = H - 1; k >= 0; --k) {
+        T *ik = act + a.in_off[k + 1];
+        T *dk = act + a.delta_off[k];
+        float dt[2][8];
+        T *ib = ik + (int64_t)(4 * q) * a.ldn + i;
+        T *db = dk + (int64_t)(4 * q) * a.ldn + i;
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) {
+            int t = 2 * c + (s >> 2), r = s & 3;
+            float h = (float)hv[k][c][s];
+            float dv = h > 0.0f ? acc[t][r] : 0.0f;
+            dt[c][s] = dv;
+            const int64_t ro = (int64_t)(hid_col_b(c, 0, s)) * a.ldn;  // row hid_col(c, q, s)
+            ib[ro] = hv[k][c][s];
+            db[ro] = to_t<T>(dv);
+          }
+        vec bd0 = M::pack(dt[0]), bd1 = M::pack(dt[1]);
+        const vec *img = (k >= 1) ? bh + (k - 1) * 8 * 64 : bh + (H - 1) * 8 * 64;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          f32x4 c = {0.f, 0.f, 0.f, 0.f};
+          c = M::mma(img[(mt * 2 + 0) * 64 + lane], bd0, c);
+          c = M::mma(img[(mt * 2 + 1) * 64 + lane], bd1, c);
+          acc[mt] = c;
+        }
+      }
+      if (valid) {
+        float gp[8], gd[8];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          gp[r] = acc[0][r];
+          gp[4 + r] = acc[1][r];
+          gd[r] = acc[2][r];
+          gd[4 + r] = acc[3][r];
+        }
+        scatter_grid_grads(a, q, x, u0, u1, gp, gd);
+      }
+    }
+    if (q == 0) wave_loss += (double)(e[0] * e[0]) + (double)(e[1] * e[1]) + (double)(e[2] * e[2]);
+  }
+  for (int off = 32; off > 0; off >>= 1) wave_loss += __shfl_down(wave_loss, off);
+  if (lane == 0 && wave_loss != 0.0) atomicAdd(a.loss, wave_loss);
+}
+
+// ------------------------------------------------------------------ weight gradients
+struct DwJob {
+  int m, ot, it;
+};
+struct DwArgs {
+  const void *act;
+  int64_t ldn;
+  int64_t delta_off, in_off;  // of this launch's layer
+  int kchunk;                 // samples per wave
+  int rows, cols;             // actual W_m size
+  float *grad;                // W_m gradient (row-major rows x cols)
+  int n_ot, n_it;
+};
+
+template <int P>
+__global__ __launch_bounds__(64) void dw_kernel(DwArgs a) {
+  typedef typename ActT<P>::type T;
+  const int lane = lane_id(), q = lane >> 4, nl = lane & 15;
+  const int tj = blockIdx.y;
+  const int ot = tj / a.n_it, it = tj % a.n_it;
+  const T *D = reinterpret_cast<const T *>(a.act) + a.delta_off + (int64_t)(16 * ot + nl) * a.ldn;
+  const T *X = reinterpret_cast<const T *>(a.act) + a.in_off + (int64_t)(16 * it + nl) * a.ldn;
+  const int64_t k0 = (int64_t)blockIdx.x * a.kchunk;
+  int64_t k1 = k0 + a.kchunk;
+  if (k1 > a.ldn) k1 = a.ldn;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (P == P_F32) {
+    for (int64_t k = k0; k < k1; k += 4)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(D[k + q], X[k + q], acc, 0, 0, 0);
+  } else {
+    typedef typename Mma<P>::vec vec;
+    for (int64_t k = k0; k < k1; k += 32) {
+      vec av = *reinterpret_cast<const vec *>(D + k + 8 * q);
+      vec bv = *reinterpret_cast<const vec *>(X + k + 8 * q);
+      acc = Mma<P>::mma(av, bv, acc);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int o = 16 * ot + 4 * q + r, c = 16 * it + nl;
+    if (o < a.rows && c < a.cols && acc[r] != 0.0f) atomicAdd(&a.grad[o * a.cols + c], acc[r]);
+  }
+}
+
+// ------------------------------------------------------------------ Adam
+struct AdamArgs {
+  float *p, *m, *v, *g;
+  size_t n, grid_floats;
+  float lr, beta1, beta2, eps, bc1, bc2, gscale;
+  uint32_t *lp16, *lpbf;  // optional 16-bit grid copies to refresh
+};
+
+__global__ void adam_kernel(AdamArgs a) {
+  size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;  // pair index
+  size_t i0 = 2 * j;
+  if (i0 >= a.n) return;
+  float out[2];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    size_t i = i0 + s;
+    if (i >= a.n) break;
+    float g = a.g[i] * a.gscale;
+    a.g[i] = 0.0f;
+    float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
+    float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    float mh = m / a.bc1, vh = v / a.bc2;
+    float p = a.p[i] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.p[i] = p;
+    out[s] = p;
+  }
+  if (i0 + 1 < a.grid_floats) {
+    if (a.lp16) {
+      __half2 h = __floats2half2_rn(out[0], out[1]);
+      a.lp16[j] = *reinterpret_cast<uint32_t *>(&h);
+    }
+    if (a.lpbf) {
+      __bf16 x = (__bf16)out[0], y = (__bf16)out[1];
+      a.lpbf[j] = (uint32_t)__builtin_bit_cast(uint16_t, x) |
+                  ((uint32_t)__builtin_bit_cast(uint16_t, y) << 16);
+    }
+  }
+}
+
+__global__ void scale_copy_kernel(const float *__restrict__ src, float *__restrict__ dst, size_t n,
+                                  float s) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i] * s;
+}
+
+// ------------------------------------------------------------------ host side
+struct TrainLayout {
+  int64_t ldn;
+  int64_t delta_off[PFN_MAX_HIDDEN + 1], in_off[PFN_MAX_HIDDEN + 1];
+  int64_t elems;
+};
+
+static TrainLayout train_layout(int H, int64_t n) {
+  TrainLayout t{};
+  t.ldn = (n + 31) / 32 * 32;
+  int64_t off = 0;
+  for (int m = 0; m <= H; ++m) {
+    t.delta_off[m] = off;
+    off += (int64_t)(m == H ? 16 : 64) * t.ldn;
+  }
+  for (int m = 0; m <= H; ++m) {
+    t.in_off[m] = off;
+    off += (int64_t)(m == 0 ? 80 : 64) * t.ldn;
+  }
+  t.elems = off;
+  return t;
+}
+
+static pfn_status ensure_train_buffers(pfn_context *ctx, FieldSlot &f, int prec, int64_t n) {
+  TrainLayout tl = train_layout(f.desc.hidden_layers, n);
+  size_t bytes = (size_t)tl.elems * (prec == P_F32 ? 4 : 2);
+  if (ctx->train_act_bytes < bytes) {
+    if (ctx->train_act) (void)hipFree(ctx->train_act);
+    ctx->train_act = nullptr;
+    ctx->train_act_bytes = 0;
+    PFN_HIP(ctx, hipMalloc(&ctx->train_act, bytes));
+    ctx->train_act_bytes = bytes;
+  }
+  PFN_HIP(ctx, hipMemsetAsync(ctx->train_act, 0, bytes, ctx->stream));
+  if (!f.mlp_bwd[prec]) {
+    PFN_HIP(ctx, hipMalloc(&f.mlp_bwd[prec],
+                           (size_t)bwd_elems(prec, f.desc.hidden_layers) * (prec == P_F32 ? 4 : 2)));
+  }
+  return PFN_OK;
+}
+
+static pfn_status refresh_train_images(pfn_context *ctx, FieldSlot &f, int prec) {
+  pfn_status st = field_refresh(ctx, f, prec);
+  if (st) return st;
+  if (!f.bwd_valid[prec]) {
+    PFN_HIP(ctx, launch_field_pack_bwd(ctx, f, prec));
+    f.bwd_valid[prec] = true;
+  }
+  return PFN_OK;
+}
+
+template <int P, int H, bool GEN>
+static hipError_t launch_fb_t(const TrainArgs &a, unsigned blocks, hipStream_t st) {
+  hipLaunchKernelGGL((train_fb_kernel<P, H, GEN>), dim3(blocks), dim3(TRAIN_THREADS), 0, st, a);
+  return hipGetLastError();
+}
+template <int P, bool GEN>
+static hipError_t launch_fb_h(const TrainArgs &a, int H, unsigned blocks, hipStream_t st) {
+  switch (H) {
+    case 1: return launch_fb_t<P, 1, GEN>(a, blocks, st);
+    case 2: return launch_fb_t<P, 2, GEN>(a, blocks, st);
+    case 3: return launch_fb_t<P, 3, GEN>(a, blocks, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template <bool GEN>
+static hipError_t launch_fb(const TrainArgs &a, int prec, int H, unsigned blocks, hipStream_t st) {
+  if (prec == P_F32) return launch_fb_h<P_F32, GEN>(a, H, blocks, st);
+  if (prec == P_BF16) return launch_fb_h<P_BF16, GEN>(a, H, blocks, st);
+  return launch_fb_h<P_F16, GEN>(a, H, blocks, st);
+}
+
+// Forward/backward over n samples into f.grad (unscaled), loss sum into *loss_dev.
+static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bool gen,
+                         const SampleSrc &src, const float *xyz, const float *dir, const float *g,
+                         const float *tgt, double *loss_dev) {
+  const int H = f.desc.hidden_layers;
+  TrainLayout tl = train_layout(H, n);
+  TrainArgs a{};
+  a.F = make_field_dev(f, prec);
+  a.fwd = f.mlp_packed[prec];
+  a.bwd = f.mlp_bwd[prec];
+  a.src = src;
+  a.in_xyz = xyz;
+  a.in_dir = dir;
+  a.in_g = g;
+  a.in_tgt = tgt;
+  a.n = n;
+  a.ldn = tl.ldn;
+  a.grad_pos = f.grad;
+  a.grad_dir = f.grad + 2 * f.pos_entries;
+  a.act = ctx->train_act;
+  for (int m = 0; m <= H; ++m) {
+    a.delta_off[m] = tl.delta_off[m];
+    a.in_off[m] = tl.in_off[m];
+  }
+  a.loss = loss_dev;
+  int64_t ntiles = tl.ldn / 16;
+  unsigned blocks = (unsigned)((ntiles + 3) / 4);
+  timing_begin(ctx);
+  PFN_HIP(ctx, gen ? launch_fb<true>(a, prec, H, blocks, ctx->stream)
+                   : launch_fb<false>(a, prec, H, blocks, ctx->stream));
+  timing_end(ctx, TK_TRAIN);
+  // weight gradients, one launch per layer
+  const int kchunk = 2048;
+  for (int m = 0; m <= H; ++m) {
+    DwArgs d{};
+    d.act = ctx->train_act;
+    d.ldn = tl.ldn;
+    d.delta_off = tl.delta_off[m];
+    d.in_off = tl.in_off[m];
+    d.kchunk = kchunk;
+    d.rows = m == H ? 3 : PFN_WIDTH;
+    d.cols = m == 0 ? 4 * f.desc.levels + 1 : PFN_WIDTH;
+    d.grad = f.grad + f.w_off[m];
+    d.n_ot = m == H ? 1 : 4;
+    d.n_it = m == 0 ? 5 : 4;
+    dim3 grid((unsigned)((tl.ldn + kchunk - 1) / kchunk), (unsigned)(d.n_ot * d.n_it));
+    if (prec == P_F32) hipLaunchKernelGGL(dw_kernel<P_F32>, grid, dim3(64), 0, ctx->stream, d);
+    else if (prec == P_BF16) hipLaunchKernelGGL(dw_kernel<P_BF16>, grid, dim3(64), 0, ctx->stream, d);
+    else hipLaunchKernelGGL(dw_kernel<P_F16>, grid, dim3(64), 0, ctx->stream, d);
+    PFN_HIP(ctx, hipGetLastError());
+  }
+  return PFN_OK;
+}
+
+static pfn_status run_adam(pfn_context *ctx, FieldSlot &f, float *grad, int64_t t, float lr,
+                           float b1, float b2, float eps, float gscale, int prec) {
+  AdamArgs a{};
+  a.p = f.master;
+  a.m = f.adam_m;
+  a.v = f.adam_v;
+  a.g = grad;
+  a.n = f.n_params;
+  a.grid_floats = f.mlp_off;
+  a.lr = lr;
+  a.beta1 = b1;
+  a.beta2 = b2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 - std::pow((double)b1, (double)t));
+  a.bc2 = (float)(1.0 - std::pow((double)b2, (double)t));
+  a.gscale = gscale;
+  a.lp16 = prec == P_F16 ? f.lp_table[P_F16] : nullptr;
+  a.lpbf = prec == P_BF16 ? f.lp_table[P_BF16] : nullptr;
+  size_t pairs = (f.n_params + 1) / 2;
+  timing_begin(ctx);
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, ctx->stream, a);
+  PFN_HIP(ctx, hipGetLastError());
+  timing_end(ctx, TK_ADAM);
+  // The master changed: every derived copy is stale, except the 16-bit grid copy of the
+  // training precision, which the Adam pass rewrote; its MLP image is repacked here.
+  field_params_changed(f);
+  if (prec != P_F32) {
+    PFN_HIP(ctx, launch_field_pack_mlp(ctx, f, prec));
+    f.lp_valid[prec] = true;
+  }
+  return PFN_OK;
+}
+
+static pfn_status check_training_field(pfn_context *ctx, FieldSlot &f) {
+  if (!f.init) return pfn_fail(ctx, PFN_ERR_NOT_READY, "field not initialised");
+  if (f.desc.hidden_layers > 3)
+    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training supports 1 to 3 hidden layers");
+  return PFN_OK;
+}
+
+static int prec_from(pfn_dtype d) { return d == PFN_F32 ? P_F32 : d == PFN_BF16 ? P_BF16 : P_F16; }
+
+static SampleSrc make_src(pfn_context *ctx, uint64_t seed, int64_t step, float psi) {
+  SampleSrc s{};
+  s.seed = seed;
+  s.step = step;
+  s.cache = ctx->cache;
+  s.cache_res = ctx->cache_res;
+  s.n_bins = ctx->cache_bins;
+  for (int b = 0; b < ctx->cache_bins; ++b) s.g_bins[b] = ctx->g_bins[b];
+  s.inv_kappa = (float)(1.0 / ctx->kappa);
+  s.psi = psi;
+  return s;
+}
+
+extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
+                                      float *xyz, float *dir, float *g, int32_t *bin, float *tgt) {
   if (!ctx) return PFN_ERR_INVALID_ARG;
-  return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training not built yet");
+  if (n < 0 || n > ((int64_t)1 << 32)) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "n in [0, 2^32]");
+  if (step < 0 || step >= ((int64_t)1 << 31))
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "step in [0, 2^31)");
+  if (!ctx->cache_valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon cache");
+  if (n == 0) return PFN_OK;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  float psi = ctx->fields[ctx->cur_field].init ? ctx->fields[ctx->cur_field].desc.psi : 5.0f;
+  SampleSrc s = make_src(ctx, seed, step, psi);
+  hipLaunchKernelGGL(train_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     ctx->stream, s, n, xyz, dir, g, bin, tgt);
+  PFN_HIP(ctx, hipGetLastError());
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype precision,
+                                                 const float *xyz, const float *dir,
+                                                 const float *g, const float *tgt, int64_t n,
+                                                 double *host_loss, float *dev_grad) {
+  if (!ctx) return PFN_ERR_INVALID_ARG;
+  if (!(precision == PFN_F32 || precision == PFN_F16 || precision == PFN_BF16))
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad precision");
+  if (n < 1 || n > ((int64_t)1 << 26)) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "n in [1, 2^26]");
+  if (!xyz || !dir || !g || !tgt) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "NULL input");
+  FieldSlot &f = ctx->fields[ctx->cur_field];
+  pfn_status st = check_training_field(ctx, f);
+  if (st) return st;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  int prec = prec_from(precision);
+  st = ensure_train_buffers(ctx, f, prec, n);
+  if (st) return st;
+  st = refresh_train_images(ctx, f, prec);
+  if (st) return st;
+  st = ensure_scratch(ctx, 64 * sizeof(double));
+  if (st) return st;
+  double *loss_dev = (double *)ctx->scratch;
+  PFN_HIP(ctx, hipMemsetAsync(loss_dev, 0, sizeof(double), ctx->stream));
+  PFN_HIP(ctx, hipMemsetAsync(f.grad, 0, f.n_params * 4, ctx->stream));
+  SampleSrc src{};
+  st = run_fb(ctx, f, prec, n, false, src, xyz, dir, g, tgt, loss_dev);
+  if (st) return st;
+  const float scale = (float)(2.0 / (3.0 * (double)n));
+  if (dev_grad) {
+    hipLaunchKernelGGL(scale_copy_kernel, dim3((unsigned)((f.n_params + 255) / 256)), dim3(256), 0,
+                       ctx->stream, f.grad, dev_grad, f.n_params, scale);
+    PFN_HIP(ctx, hipGetLastError());
+  }
+  double loss = 0.0;
+  PFN_HIP(ctx, hipMemcpyAsync(&loss, loss_dev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  PFN_HIP(ctx, hipMemsetAsync(f.grad, 0, f.n_params * 4, ctx->stream));
+  PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (host_loss) *host_loss = loss / (3.0 * (double)n);
+  if (!std::isfinite(loss)) return pfn_fail(ctx, PFN_ERR_NUMERIC, "loss is not finite");
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_field_adam_step(pfn_context *ctx, const float *dev_grad, int64_t t,
+                                          float lr, float beta1, float beta2, float eps) {
+  if (!ctx) return PFN_ERR_INVALID_ARG;
+  if (!dev_grad) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "gradient is NULL");
+  if (t < 1) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "t >= 1");
+  if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps >= 0.0f))
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  FieldSlot &f = ctx->fields[ctx->cur_field];
+  if (!f.init) return pfn_fail(ctx, PFN_ERR_NOT_READY, "field not initialised");
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  // the kernel clears the gradient it reads: work on a copy
+  PFN_HIP(ctx, hipMemcpyAsync(f.grad, dev_grad, f.n_params * 4, hipMemcpyDeviceToDevice, ctx->stream));
+  pfn_status st = run_adam(ctx, f, f.grad, t, lr, beta1, beta2, eps, 1.0f, P_F32);
+  if (st) return st;
+  f.adam_t = t;
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *p, float *hist) {
+  if (!ctx) return PFN_ERR_INVALID_ARG;
+  if (!p) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "params are NULL");
+  if (p->steps < 1 || p->steps > 1000000) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "steps in [1, 1e6]");
+  if (p->log2_batch < 4 || p->log2_batch > 22)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "log2_batch in [4, 22]");
+  if (!(p->lr > 0.0f) || !(p->beta1 >= 0.0f && p->beta1 < 1.0f) ||
+      !(p->beta2 >= 0.0f && p->beta2 < 1.0f) || !(p->eps >= 0.0f) || !(p->decay > 0.0f) ||
+      p->decay_interval < 1 || p->decay_start < 0)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad optimiser hyper-parameters");
+  if (!(p->precision == PFN_F32 || p->precision == PFN_F16 || p->precision == PFN_BF16))
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad precision");
+  if (!ctx->cache_valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon cache");
+  FieldSlot &f = ctx->fields[ctx->cur_field];
+  pfn_status st = check_training_field(ctx, f);
+  if (st) return st;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  const int prec = prec_from(p->precision);
+  const int64_t n = (int64_t)1 << p->log2_batch;
+  st = ensure_train_buffers(ctx, f, prec, n);
+  if (st) return st;
+  st = ensure_scratch(ctx, sizeof(double) * (size_t)p->steps + 64);
+  if (st) return st;
+  double *loss_dev = (double *)ctx->scratch;
+  PFN_HIP(ctx, hipMemsetAsync(loss_dev, 0, sizeof(double) * p->steps, ctx->stream));
+  f.kappa = ctx->kappa;
+  const float scale = (float)(2.0 / (3.0 * (double)n));
+  for (int s = 0; s < p->steps; ++s) {
+    st = refresh_train_images(ctx, f, prec);
+    if (st) return st;
+    SampleSrc src = make_src(ctx, p->seed, s, f.desc.psi);
+    st = run_fb(ctx, f, prec, n, true, src, nullptr, nullptr, nullptr, nullptr, loss_dev + s);
+    if (st) return st;
+    double lr = p->lr;
+    if (s >= p->decay_start)
+      lr *= std::pow((double)p->decay, (double)(1 + (s - p->decay_start) / p->decay_interval));
+    st = run_adam(ctx, f, f.grad, f.adam_t + 1, (float)lr, p->beta1, p->beta2, p->eps, scale, prec);
+    if (st) return st;
+    f.adam_t += 1;
+  }
+  std::vector<double> h(p->steps);
+  PFN_HIP(ctx, hipMemcpyAsync(h.data(), loss_dev, sizeof(double) * p->steps,
+                              hipMemcpyDeviceToHost, ctx->stream));
+  PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  bool finite = true;
+  for (int s = 0; s < p->steps; ++s) {
+    double l = h[s] / (3.0 * (double)n);
+    if (hist) hist[s] = (float)l;
+    finite &= std::isfinite(l);
+  }
+  if (!finite) return pfn_fail(ctx, PFN_ERR_NUMERIC, "training loss became NaN or Inf");
+  return PFN_OK;
 }

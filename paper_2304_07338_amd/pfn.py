@@ -356,3 +356,11 @@ class Context:
         ms, n = C.c_double(), C.c_int64()
         self._ok(self.lib.pfn_timing_get(self.h, kernel, C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def count_enable(self, on: bool = True):
+        self._ok(self.lib.pfn_count_enable(self.h, int(on)))
+
+    def count_get(self):
+        st, q = C.c_uint64(), C.c_uint64()
+        self._ok(self.lib.pfn_count_get(self.h, C.byref(st), C.byref(q)))
+        return st.value, q.value

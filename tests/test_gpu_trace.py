@@ -1,0 +1,110 @@
+"""Parity of the HIP photon tracer and cache with the FP64 oracle (same Philox streams, same
+global majorant: photon-by-photon agreement up to rare FP32/FP64 decision flips)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import gpu_context, oracle_scene, say, scene_arrays
+from paper_2304_07338_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+BINS = [-0.6, 0.0, 0.7]
+
+
+@pytest.fixture(scope="module")
+def traced(orc):
+    w, vol, tf, _ = scene_arrays("c0")
+    lights = sg.lights_array(sg.make_lights(2, 31))
+    ctx = gpu_context(vol, tf, lights)
+    n = 30011  # not a multiple of lights x bins: uneven (light, bin) groups
+    say(f"trace {n} photons, 2 lights, 3 bins")
+    st = ctx.trace_photon_cache(n, BINS, cache_res=16, seed=77, max_collisions=8, rr_start=3)
+    recs = {k: v.cpu().numpy() for k, v in ctx.get_records(n * 7).items()}
+    os_ = oracle_scene(orc, vol, tf, lights)
+    ost, orecs = orc.trace(os_, n, BINS, seed=77, max_collisions=8, rr_start=3)
+    return dict(ctx=ctx, st=st, recs=recs, ost=ost, orecs=orecs, os=os_, n=n)
+
+
+def test_records_match_photon_by_photon(traced):
+    g, o = traced["recs"], traced["orecs"]
+    n = traced["n"]
+    gc = np.bincount(g["photon"], minlength=n)
+    oc = np.bincount(o["photon"].astype(np.int64), minlength=n)
+    same = gc == oc
+    say("  photons with equal record counts:", same.mean(), "records", len(g["x"]), len(o["x"]))
+    assert same.mean() >= 0.995
+    assert traced["st"]["n_records"] == len(g["x"])
+    # compare the records of the photons whose paths agree in length
+    gs = np.concatenate([[0], np.cumsum(gc)])
+    os_ = np.concatenate([[0], np.cumsum(oc)])
+    ids = np.flatnonzero(same & (gc > 0))
+    gi = np.concatenate([np.arange(gs[i], gs[i + 1]) for i in ids])
+    oi = np.concatenate([np.arange(os_[i], os_[i + 1]) for i in ids])
+    dx = np.abs(g["x"][gi] - o["x"][oi]).max(axis=1)
+    dw = np.abs(g["w"][gi] - o["w"][oi]).max(axis=1)
+    dp = (np.abs(g["power"][gi] - o["power"][oi]) / o["power"][oi].max(axis=1, keepdims=True)).max(axis=1)
+    say("  |dx| p99", np.quantile(dx, 0.99), "|dw| p99", np.quantile(dw, 0.99), "|dp| p99",
+        np.quantile(dp, 0.99))
+    assert np.quantile(dx, 0.99) < 1e-4 and np.quantile(dw, 0.99) < 1e-4
+    assert np.quantile(dp, 0.99) < 1e-5
+    np.testing.assert_array_equal(g["bin"][gi], o["bin"][oi])
+
+
+def test_tallies_match_and_balance(traced):
+    st, ost = traced["st"], traced["ost"]
+    np.testing.assert_allclose(st["emitted"], ost["emitted"], rtol=1e-6)
+    np.testing.assert_allclose(st["entered"], ost["entered"], rtol=1e-3)
+    for k in ("escaped", "absorbed", "stored"):
+        np.testing.assert_allclose(st[k], ost[k], rtol=2e-2)
+    bal = st["escaped"] + st["absorbed"] + st["truncated"] + st["rr_killed"]
+    # with roulette the balance holds in expectation: a few percent at this photon count
+    assert np.all(np.abs(bal / st["emitted"] - 1) < 0.05)
+    assert abs(st["collisions"] / ost["collisions"] - 1) < 1e-2
+
+
+def test_energy_balance_exact_without_roulette(orc):
+    w, vol, tf, lights = scene_arrays("c0")
+    ctx = gpu_context(vol, tf, lights)
+    st = ctx.trace_photon_cache(20000, [0.3], cache_res=8, seed=5, max_collisions=12, rr_start=0)
+    bal = st["escaped"] + st["absorbed"] + st["truncated"] + st["rr_killed"]
+    np.testing.assert_allclose(bal, st["emitted"], rtol=1e-5)
+    d = np.linalg.norm(lights[0, :3] - 0.5)
+    share = 0.5 * (1 - math.sqrt(1 - 0.75 / d ** 2)) if d > math.sqrt(0.75) else 1.0
+    np.testing.assert_allclose(st["emitted"], 4 * math.pi * share * lights[0, 3:], rtol=1e-6)
+
+
+def test_cache_from_identical_records(orc, traced):
+    import torch
+    ctx = traced["ctx"]
+    cache = ctx.get_cache().cpu().numpy()
+    nb, res, kappa = ctx.cache_info()
+    assert (nb, res) == (3, 16)
+    g = traced["recs"]
+    ref, okappa = orc.splat_cache(traced["os"], {"x": g["x"].astype(np.float64),
+                                                 "power": g["power"].astype(np.float64),
+                                                 "bin": g["bin"]}, 16, 3)
+    err = np.abs(cache - ref).max() / ref.max()
+    say("  cache max rel diff", err, "kappa", kappa, okappa)
+    assert err < 1e-5
+    assert kappa == pytest.approx(cache.max(), rel=1e-7)
+    assert kappa == pytest.approx(okappa, rel=1e-5)
+
+
+def test_get_records_capacity(traced):
+    r = traced["ctx"].get_records(100)
+    assert r["x"].shape == (100, 3)
+    full = traced["recs"]
+    np.testing.assert_array_equal(r["x"].cpu().numpy(), full["x"][:100])
+
+
+def test_trace_rejects_bad_params(traced):
+    from paper_2304_07338_amd.pfn import PfnError
+    ctx = traced["ctx"]
+    for kw in (dict(g_bins=[0.5, 0.1]), dict(g_bins=[0.99]), dict(cache_res=1),
+               dict(max_collisions=0)):
+        args = dict(n_photons=100, g_bins=[0.0], cache_res=8)
+        args.update(kw)
+        with pytest.raises(PfnError):
+            ctx.trace_photon_cache(**args)

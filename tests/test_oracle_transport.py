@@ -16,6 +16,13 @@ def gray_tf(albedo, opacity):
     return tf
 
 
+def cone_share(p):
+    """Share of the full sphere of directions in the emission cone toward the cube."""
+    d = np.linalg.norm(np.asarray(p) - 0.5)
+    R = math.sqrt(3) / 2
+    return 1.0 if d <= R else 0.5 * (1 - math.sqrt(1 - (R / d) ** 2))
+
+
 def homog_scene(orc, rho, albedo=0.7, opacity=None, ext=20.0, lights=None, n=8):
     tf = gray_tf(albedo, 1.0 if opacity is None else opacity)
     if opacity is None:
@@ -37,8 +44,8 @@ def test_tracer_energy_conservation_exact_without_roulette(orc, albedo):
     st, _ = orc.trace(s, 6000, [-0.5, 0.0, 0.6], seed=5, rr_start=0, max_collisions=64,
                       want_records=False)
     # every HG bin is a complete photon map of the scene: per bin, each light emits exactly
-    # 4 pi I, split over that (light, bin) pair's photons
-    emitted_expected = 3 * 4 * math.pi * lights[:, 3:].sum(axis=0)
+    # 4 pi I into its emission cone's share of directions, split over the pair's photons
+    emitted_expected = 3 * 4 * math.pi * sum(cone_share(L[:3]) * L[3:] for L in lights)
     np.testing.assert_allclose(st["emitted"], emitted_expected, rtol=1e-12)
     balance = st["escaped"] + st["absorbed"] + st["truncated"] + st["rr_killed"]
     np.testing.assert_allclose(balance, st["emitted"], rtol=1e-12)  # misses count as escaped
@@ -110,9 +117,26 @@ def test_tracer_stratification_over_lights_and_bins(orc):
     s = homog_scene(orc, 0.5, albedo=0.9, lights=lights)
     bins = [-0.8, -0.4, 0.0, 0.4, 0.8]
     st, recs = orc.trace(s, 3000 + 7, bins, seed=4)
-    np.testing.assert_allclose(st["emitted"], 5 * 3 * 4 * math.pi, rtol=1e-12)
+    np.testing.assert_allclose(st["emitted"], 5 * 4 * math.pi * sum(cone_share(L[:3]) for L in lights),
+                               rtol=1e-12)
     ids = recs["photon"]
     np.testing.assert_array_equal(recs["bin"], (ids // 3) % 5)
+
+
+def test_tracer_entered_power_is_the_solid_angle_of_the_cube(orc):
+    """A light on the z axis at height 2 sees the cube's top face (side 1, distance 1) as its
+    silhouette: the power entering the cube is I * Omega with
+    Omega = 4 arcsin(a b / sqrt((a^2 + 4 d^2)(b^2 + 4 d^2))) = 4 arcsin(1/5) (solid angle of a
+    centred rectangle).  Independent of how the emitter samples directions."""
+    s = homog_scene(orc, 0.5, albedo=0.9, lights=np.array([[0.5, 0.5, 2.0, 1.0, 2.0, 0.5]]))
+    n = 200000
+    st, _ = orc.trace(s, n, [0.0], seed=8, want_records=False)
+    omega = 4 * math.asin(1 / 5)
+    expect = omega * np.array([1.0, 2.0, 0.5])
+    frac_hit = st["entered"][0] / st["emitted"][0]
+    sd = math.sqrt(frac_hit * (1 - frac_hit) / n) * st["emitted"][0]
+    assert np.all(np.abs(st["entered"] - expect) < 5 * sd * np.array([1.0, 2.0, 0.5]))
+    assert frac_hit > 0.3  # the cone keeps most photons on the volume
 
 
 def test_cache_mass_conservation(orc):
