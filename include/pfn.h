@@ -45,14 +45,15 @@ typedef struct pfn_context pfn_context;
 
 /* ------------------------------------------------------------------ context */
 /* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t) is used for all work;
- * NULL makes the library create and own a stream. */
+ * NULL selects the device's null stream (ordered with every blocking stream, e.g. PyTorch's
+ * default stream). */
 pfn_status pfn_create(int device, void *hip_stream, pfn_context **out);
 /* Free every context-owned buffer (volume bricks, caches, records, fields, optimiser state). */
 void pfn_destroy(pfn_context *ctx);
 /* Text of the last error on this context; valid until the next call on it. */
 const char *pfn_last_error(const pfn_context *ctx);
 pfn_status pfn_sync(pfn_context *ctx);
-/* Replace the stream used for subsequent work (NULL = the library-owned stream). */
+/* Replace the stream used for subsequent work (NULL = the null stream); waits for the old one. */
 pfn_status pfn_set_stream(pfn_context *ctx, void *hip_stream);
 
 /* ------------------------------------------------------------------ scene */
@@ -230,6 +231,16 @@ pfn_status pfn_image_error(pfn_context *ctx, const float *dev_img, const float *
 /* Tile shape of the ray-march launch: each wave covers tile_w x (64 / tile_w) pixels and a
  * workgroup block_w x block_h waves (block_w * block_h = 4).  Chosen by the autotuner. */
 pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int block_h);
+/* Launch mode of the ray march: persistent_per_cu = 0 launches one workgroup per pixel block;
+ * k > 0 launches k workgroups per compute unit that pull blocks from per-XCD queues until all
+ * jobs are done.  use_graph != 0 captures each distinct launch into a HIP graph on first use and
+ * replays it afterwards (the job table is refreshed before every replay). */
+pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_graph);
+/* Autotuner: time every tile shape / block arrangement / launch mode on this batch (iters
+ * launches each), keep the fastest for the context and return it (cached per batch shape). */
+pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs,
+                              int iters, int *host_tile_w, int *host_block_w, int *host_block_h,
+                              int *host_persistent, double *host_ms);
 
 /* ------------------------------------------------------------------ timing */
 /* When enabled, the main kernels are bracketed by HIP events on the stream they run on; the

@@ -103,6 +103,10 @@ SIGNATURES = {
     "pfn_image_error": (C.c_int, [ctxp, vp, vp, C.c_int64, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pfn_set_tile_config": (C.c_int, [ctxp, C.c_int, C.c_int, C.c_int]),
+    "pfn_set_launch_mode": (C.c_int, [ctxp, C.c_int, C.c_int]),
+    "pfn_autotune_batch": (C.c_int, [ctxp, C.POINTER(RenderJob), C.c_int, C.c_int,
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "pfn_timing_enable": (C.c_int, [ctxp, C.c_int]),
     "pfn_timing_get": (C.c_int, [ctxp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pfn_timing_reset": (C.c_int, [ctxp]),

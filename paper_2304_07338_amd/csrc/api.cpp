@@ -98,15 +98,9 @@ extern "C" pfn_status pfn_create(int device, void *hip_stream, pfn_context **out
   pfn_context *ctx = new (std::nothrow) pfn_context();
   if (!ctx) return PFN_ERR_OUT_OF_MEMORY;
   ctx->device = device;
-  if (hip_stream) {
-    ctx->stream = (hipStream_t)hip_stream;
-  } else {
-    if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess) {
-      delete ctx;
-      return PFN_ERR_HIP;
-    }
-    ctx->stream = ctx->own_stream;
-  }
+  // NULL selects the device's null stream, which orders the library's work with every other
+  // user of that stream (e.g. PyTorch's default stream)
+  ctx->stream = (hipStream_t)hip_stream;
   *out = ctx;
   return PFN_OK;
 }
@@ -146,8 +140,14 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   dev_free(ctx->fields_dev);
   dev_free(ctx->mlp_ptrs_dev);
   dev_free(ctx->counters);
+  dev_free(ctx->queues);
+  for (auto &g : ctx->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  ctx->graphs.clear();
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
   delete ctx;
 }
 
@@ -165,11 +165,7 @@ extern "C" pfn_status pfn_sync(pfn_context *ctx) {
 extern "C" pfn_status pfn_set_stream(pfn_context *ctx, void *hip_stream) {
   CHECK_CTX(ctx);
   PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  ctx->stream = hip_stream ? (hipStream_t)hip_stream : ctx->own_stream;
-  if (!ctx->stream) {
-    PFN_HIP(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
-    ctx->stream = ctx->own_stream;
-  }
+  ctx->stream = (hipStream_t)hip_stream;
   return PFN_OK;
 }
 
@@ -675,14 +671,53 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
   a.block_w = tc.block_w;
   a.block_h = tc.block_h;
   a.counters = nullptr;
+  a.persistent = tc.persistent;
+  if (tc.persistent) {
+    if (!ctx->queues) PFN_HIP(ctx, dev_alloc((void **)&ctx->queues, 64));
+    a.queues = ctx->queues;
+  }
   if (ctx->counting) {
     if (!ctx->counters) PFN_HIP(ctx, dev_alloc((void **)&ctx->counters, 16));
     PFN_HIP(ctx, hipMemsetAsync(ctx->counters, 0, 16, ctx->stream));
     a.counters = ctx->counters;
   }
-  timing_begin(ctx);
-  PFN_HIP(ctx, launch_march(a, ctx->vol_dtype, p0.direct, p0.indirect, prec, ctx->stream));
-  timing_end(ctx, TK_MARCH);
+  if (ctx->use_graph) {
+    // replay a captured launch with the same arguments (the job table, field descriptors and
+    // weight pointers it reads were refreshed above); capture it on first use
+    std::vector<unsigned char> key(sizeof(MarchArgs) + 4 * sizeof(int));
+    std::memcpy(key.data(), &a, sizeof(MarchArgs));
+    int extra[4] = {(int)ctx->vol_dtype, p0.direct, p0.indirect, prec};
+    std::memcpy(key.data() + sizeof(MarchArgs), extra, sizeof(extra));
+    MarchGraph *g = nullptr;
+    for (auto &e : ctx->graphs)
+      if (e.key == key) g = &e;
+    if (!g) {
+      if (ctx->graphs.size() >= 16) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        (void)hipGraphDestroy(ctx->graphs.front().graph);
+        ctx->graphs.erase(ctx->graphs.begin());
+      }
+      if (!ctx->cap_stream)
+        PFN_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+      MarchGraph ng;
+      ng.key = key;
+      PFN_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+      hipError_t le = launch_march(a, ctx->vol_dtype, p0.direct, p0.indirect, prec, ctx->cap_stream);
+      hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &ng.graph);
+      if (le != hipSuccess) return pfn_hip(ctx, le, "launch_march (capture)");
+      if (ce != hipSuccess) return pfn_hip(ctx, ce, "hipStreamEndCapture");
+      PFN_HIP(ctx, hipGraphInstantiate(&ng.exec, ng.graph, nullptr, nullptr, 0));
+      ctx->graphs.push_back(ng);
+      g = &ctx->graphs.back();
+    }
+    timing_begin(ctx);
+    PFN_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
+    timing_end(ctx, TK_MARCH);
+  } else {
+    timing_begin(ctx);
+    PFN_HIP(ctx, launch_march(a, ctx->vol_dtype, p0.direct, p0.indirect, prec, ctx->stream));
+    timing_end(ctx, TK_MARCH);
+  }
   if (ctx->counting) {
     PFN_HIP(ctx, hipMemcpyAsync(ctx->last_counts, ctx->counters, 16, hipMemcpyDeviceToHost,
                                 ctx->stream));
@@ -761,6 +796,105 @@ extern "C" pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int bloc
   ctx->tile.tile_h = 64 / tile_w;
   ctx->tile.block_w = block_w;
   ctx->tile.block_h = block_h;
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_graph) {
+  CHECK_CTX(ctx);
+  ARG(persistent_per_cu >= 0 && persistent_per_cu <= 16, "persistent_per_cu in [0, 16]");
+  ctx->tile.persistent = persistent_per_cu;
+  ctx->use_graph = use_graph != 0;
+  return PFN_OK;
+}
+
+// Time every candidate launch shape on the given batch and keep the fastest; results are cached
+// per (batch shape, modes, volume) in the context.
+extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs,
+                                         int iters, int *out_tile_w, int *out_block_w,
+                                         int *out_block_h, int *out_persistent, double *out_ms) {
+  CHECK_CTX(ctx);
+  ARG(jobs && n_jobs >= 1 && n_jobs <= 4096, "1 to 4096 jobs");
+  ARG(iters >= 1 && iters <= 100, "iters in [1, 100]");
+  for (int i = 0; i < n_jobs; ++i) {
+    pfn_status st = check_camera(ctx, &jobs[i].cam);
+    if (st) return st;
+    st = check_render_params(ctx, &jobs[i].params);
+    if (st) return st;
+    ARG(jobs[i].dev_rgb_out, "job output is NULL");
+    ARG(jobs[i].params.indirect == jobs[0].params.indirect &&
+            jobs[i].params.direct == jobs[0].params.direct &&
+            jobs[i].params.field_precision == jobs[0].params.field_precision,
+        "batched jobs must share indirect/direct mode and field precision");
+  }
+  pfn_status st = need_scene(ctx);
+  if (st) return st;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  // cache key: job sizes and modes, volume shape
+  std::vector<unsigned char> key;
+  auto put = [&key](const void *p, size_t n) {
+    const unsigned char *c = (const unsigned char *)p;
+    key.insert(key.end(), c, c + n);
+  };
+  for (int i = 0; i < n_jobs; ++i) {
+    put(&jobs[i].cam.width, sizeof(int));
+    put(&jobs[i].cam.height, sizeof(int));
+    put(&jobs[i].params.spp, sizeof(int));
+  }
+  put(&jobs[0].params.indirect, sizeof(int));
+  put(&jobs[0].params.direct, sizeof(int));
+  put(&jobs[0].params.field_precision, sizeof(int));
+  put(&ctx->vol_grid, sizeof(BrickGrid));
+  put(&ctx->vol_dtype, sizeof(int));
+  TileConfig best{};
+  double best_ms = -1.0;
+  for (auto &e : ctx->tuned)
+    if (e.first == key) best = e.second, best_ms = 0.0;
+  if (best_ms < 0.0) {
+    hipEvent_t e0, e1;
+    PFN_HIP(ctx, hipEventCreate(&e0));
+    PFN_HIP(ctx, hipEventCreate(&e1));
+    const int tws[3] = {8, 16, 32};
+    const int arr[3][2] = {{2, 2}, {4, 1}, {1, 4}};
+    const int pers[3] = {0, 2, 4};
+    bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;
+    ctx->use_graph = false;
+    ctx->timing = false;
+    for (int tw : tws)
+      for (auto &ar : arr)
+        for (int pz : pers) {
+          TileConfig tc;
+          tc.tile_w = tw;
+          tc.tile_h = 64 / tw;
+          tc.block_w = ar[0];
+          tc.block_h = ar[1];
+          tc.persistent = pz;
+          st = run_march(ctx, jobs, n_jobs, tc);  // warm-up
+          if (st) break;
+          PFN_HIP(ctx, hipEventRecord(e0, ctx->stream));
+          for (int it = 0; it < iters && !st; ++it) st = run_march(ctx, jobs, n_jobs, tc);
+          PFN_HIP(ctx, hipEventRecord(e1, ctx->stream));
+          PFN_HIP(ctx, hipEventSynchronize(e1));
+          float ms = 0.0f;
+          PFN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+          double per = ms / iters;
+          if (best_ms < 0.0 || per < best_ms) {
+            best_ms = per;
+            best = tc;
+          }
+        }
+    ctx->use_graph = saved_graph;
+    ctx->timing = saved_timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    ctx->tuned.push_back({key, best});
+  }
+  ctx->tile = best;
+  if (out_tile_w) *out_tile_w = best.tile_w;
+  if (out_block_w) *out_block_w = best.block_w;
+  if (out_block_h) *out_block_h = best.block_h;
+  if (out_persistent) *out_persistent = best.persistent;
+  if (out_ms) *out_ms = best_ms;
   return PFN_OK;
 }
 

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "../../include/pfn.h"
 #include "pfn_device.h"
 #include "pfn_field_dev.h"
@@ -36,6 +38,8 @@ struct MarchArgs {
   int n_jobs, total_blocks;
   int tile_w, tile_h, block_w, block_h;  // lanes per tile row/column, tiles per block row/column
   unsigned long long *counters;          // optional: [0] march steps, [1] field/cache queries
+  int persistent;                        // 0: one workgroup per block; k > 0: k workgroups per CU
+  unsigned *queues;                      // 8 per-XCD block counters (persistent mode)
 };
 
 hipError_t launch_march(const MarchArgs &a, pfn_dtype vol_dtype, int direct, int ind, int prec,

@@ -145,38 +145,41 @@ __device__ f3 field_eval_wave(const FieldDev &F, const void *lds_w, f3 xq, float
           decode_lp(r2, F.psi, F.kappa)};
 }
 
-template <typename VT, int DIRECT, int IND, int P>
-__global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
-  __shared__ float4 tf[256];
-  extern __shared__ __align__(16) unsigned char lds_w[];
-
-  // XCD-aware block order: the hardware deals blocks round-robin to the 8 XCDs, so give each
-  // XCD a contiguous run of logical blocks (neighbouring image blocks share its L2).
-  const int nb = a.total_blocks;
-  const int per = (nb + 7) >> 3;
-  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (b >= nb) return;
-
-  // job of this block: last job whose first block is <= b
+// Job of logical block b: the last job whose first block is <= b.
+__device__ __forceinline__ int find_job(const MarchArgs &a, int b) {
   int lo = 0, hi = a.n_jobs - 1;
   while (lo < hi) {
     int mid = (lo + hi + 1) >> 1;
     if (a.jobs[mid].block_begin <= b) lo = mid;
     else hi = mid - 1;
   }
-  const MarchJob job = a.jobs[lo];
+  return lo;
+}
 
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) {
-    float4 e = a.tf[i];
-    tf[i] = e;
+// Pop the next logical block from the per-XCD queues: XCD x owns the contiguous block range
+// [x*per, (x+1)*per) so that neighbouring image blocks share that XCD's L2; a workgroup whose
+// own queue is empty takes work from the others.  Returns -1 when every queue is empty, which
+// every workgroup reaches after at most 8 failed pops.
+__device__ __forceinline__ int pop_block(unsigned *queues, int xcd, int nb) {
+  const int per = (nb + 7) >> 3;
+  for (int k = 0; k < 8; ++k) {
+    const int x = (xcd + k) & 7;
+    const int begin = x * per;
+    const int size = min(per, nb - begin);
+    if (size <= 0) continue;
+    unsigned v = atomicAdd(&queues[x], 1u);
+    if (v < (unsigned)size) return begin + (int)v;
   }
-  FieldDev F;
-  if constexpr (IND == PFN_INDIRECT_FIELD) {
-    F = a.fields[job.slot];
-    stage_weights(lds_w, a.mlp[job.slot], a.mlp_bytes);
-  }
-  __syncthreads();
+  return -1;
+}
 
+// One block of 4 wave tiles of one job.
+template <typename VT, int DIRECT, int IND, int P>
+__device__ __forceinline__ void march_block(const MarchArgs &a, const MarchJob &job, int b,
+                                            const float4 *tf, const FieldDev &F,
+                                            const void *lds_w) {
+  // F refers to the job's field descriptor in global memory: the encoder indexes its per-level
+  // arrays with lane-dependent levels, which a private copy would have to keep in scratch.
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int lb = b - job.block_begin;
@@ -306,6 +309,50 @@ __global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
   }
 }
 
+template <typename VT, int DIRECT, int IND, int P>
+__global__ __launch_bounds__(MARCH_THREADS) void march_kernel(MarchArgs a) {
+  __shared__ float4 tf[256];
+  __shared__ int s_block;
+  extern __shared__ __align__(16) unsigned char lds_w[];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) tf[i] = a.tf[i];
+  const int nb = a.total_blocks;
+  if (!a.persistent) {
+    // XCD-aware block order: the hardware deals workgroups round-robin to the 8 XCDs, so give
+    // each XCD a contiguous run of logical blocks.
+    const int per = (nb + 7) >> 3;
+    const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    if (b >= nb) return;
+    const MarchJob job = a.jobs[find_job(a, b)];
+    if constexpr (IND == PFN_INDIRECT_FIELD) stage_weights(lds_w, a.mlp[job.slot], a.mlp_bytes);
+    __syncthreads();
+    march_block<VT, DIRECT, IND, P>(a, job, b, tf, a.fields[job.slot], lds_w);
+    return;
+  }
+  // persistent: workgroups pull blocks from the queues until all are empty
+  int staged = -1;
+  const int xcd = (int)(blockIdx.x & 7);
+  for (;;) {
+    if (threadIdx.x == 0) s_block = pop_block(a.queues, xcd, nb);
+    __syncthreads();
+    const int b = s_block;
+    if (b < 0) break;
+    const MarchJob job = a.jobs[find_job(a, b)];
+    if constexpr (IND == PFN_INDIRECT_FIELD) {
+      if (job.slot != staged) {
+        stage_weights(lds_w, a.mlp[job.slot], a.mlp_bytes);
+        staged = job.slot;
+      }
+    }
+    __syncthreads();
+    march_block<VT, DIRECT, IND, P>(a, job, b, tf, a.fields[job.slot], lds_w);
+    __syncthreads();  // all waves are done with s_block and the staged weights
+  }
+}
+
+__global__ void reset_queues_kernel(unsigned *q) {
+  if (threadIdx.x < 8) q[threadIdx.x] = 0u;
+}
+
 // ------------------------------------------------------------------ host side
 template <typename VT, int DIRECT, int IND, int P>
 static hipError_t launch_t(const MarchArgs &a, int blocks, size_t lds, hipStream_t st) {
@@ -346,6 +393,11 @@ hipError_t launch_march(const MarchArgs &a, pfn_dtype vol_dtype, int direct, int
   size_t lds = 0;
   if (ind == PFN_INDIRECT_FIELD) lds = (size_t)a.mlp_bytes;
   int blocks = ((a.total_blocks + 7) / 8) * 8;
+  if (a.persistent) {
+    hipLaunchKernelGGL(reset_queues_kernel, dim3(1), dim3(64), 0, st, a.queues);
+    int want = 256 * a.persistent;  // workgroups per CU x CUs
+    blocks = std::min(blocks, ((want + 7) / 8) * 8);
+  }
   if (vol_dtype == PFN_F16) return launch_d<__half>(a, direct, ind, prec, blocks, lds, st);
   return launch_d<float>(a, direct, ind, prec, blocks, lds, st);
 }

@@ -37,12 +37,19 @@ struct FieldSlot {
 
 struct TileConfig {
   int tile_w = 8, tile_h = 8, block_w = 2, block_h = 2;
+  int persistent = 0;  // 0: one workgroup per block; k: k persistent workgroups per CU
+};
+
+// A captured ray-march launch, replayed while its launch arguments stay the same.
+struct MarchGraph {
+  std::vector<unsigned char> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 struct pfn_context {
   int device = 0;
-  hipStream_t stream = nullptr;
-  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;  // nullptr = the device's null stream
   std::string err;
 
   // scene
@@ -88,7 +95,12 @@ struct pfn_context {
   size_t jobs_cap = 0;
   FieldDev *fields_dev = nullptr;
   void **mlp_ptrs_dev = nullptr;
+  unsigned *queues = nullptr;     // per-XCD block queues of the persistent launch
   TileConfig tile;
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<MarchGraph> graphs;
+  std::vector<std::pair<std::vector<unsigned char>, TileConfig>> tuned;  // autotuner cache
 
   // training activations / deltas (neuron-major, 16-bit or FP32)
   void *train_act = nullptr;

@@ -311,7 +311,7 @@ class Context:
         self._ok(self.lib.pfn_render_frame(self.h, C.byref(c), C.byref(p), _ptr(out)))
         return out
 
-    def render_batch(self, cams: List, cfgs: List[RenderConfig], outs=None):
+    def _jobs(self, cams, cfgs, outs):
         import torch
         n = len(cams)
         jobs = (_ffi.RenderJob * n)()
@@ -322,8 +322,23 @@ class Context:
             jobs[i].cam = camera_struct(cams[i])
             jobs[i].params = cfgs[i].struct()
             jobs[i].dev_rgb_out = _ptr(outs[i])
-        self._ok(self.lib.pfn_render_batch(self.h, jobs, n))
+        return jobs, outs
+
+    def render_batch(self, cams: List, cfgs: List[RenderConfig], outs=None):
+        jobs, outs = self._jobs(cams, cfgs, outs)
+        self._ok(self.lib.pfn_render_batch(self.h, jobs, len(cams)))
         return outs
+
+    def autotune_batch(self, cams: List, cfgs: List[RenderConfig], outs=None, iters: int = 2):
+        jobs, outs = self._jobs(cams, cfgs, outs)
+        tw, bw, bh, pz, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        self._ok(self.lib.pfn_autotune_batch(self.h, jobs, len(cams), iters, C.byref(tw),
+                                             C.byref(bw), C.byref(bh), C.byref(pz), C.byref(ms)))
+        return dict(tile_w=tw.value, block_w=bw.value, block_h=bh.value, persistent=pz.value,
+                    ms=ms.value)
+
+    def set_launch_mode(self, persistent_per_cu: int = 0, use_graph: bool = False):
+        self._ok(self.lib.pfn_set_launch_mode(self.h, persistent_per_cu, int(use_graph)))
 
     def render_path_traced(self, cam, spp: int, max_bounces: int = 8, g: float = 0.0,
                            rr_start: int = 0, light_mask: int = 0, seed: int = 0, out=None):
