@@ -1,0 +1,55 @@
+"""Profiling driver: renders the 1080p photon-field frame of the benchmark (512^3 f16 volume,
+field every 4 steps, FP16 matrix cores) a few times, plus one plain device copy of 1 GiB whose
+memory counters calibrate the HBM traffic counters.  The field keeps its initial parameters:
+the memory access pattern of a frame does not depend on the parameter values.
+
+    python -m paper_2304_07338_amd.profile_run [--frames 3]
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=3)
+    ap.add_argument("--precision", default="f16")
+    args = ap.parse_args()
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import (Context, FieldConfig, RenderConfig, DIRECT_LIGHT_VOLUME,
+                                          INDIRECT_FIELD)
+    w = wl.C2
+    vol, tf, lights = wl.make_scene(w, device="cuda:0")
+    ctx = Context(0)
+    ctx.set_volume(vol.contiguous())
+    ctx.set_transfer_function(tf, w.extinction)
+    ctx.set_lights(sg.lights_array(lights))
+    ctx.build_light_volume(0.5)
+    ctx.trace_photon_cache(1 << 22, wl.C1_G_BINS, cache_res=128, seed=6)
+    ctx.field_init(FieldConfig(), seed=1)
+    cam = wl.camera(w, 0)
+    rc = RenderConfig(spp=1, step_voxels=0.5, max_steps=1024, t_min=1e-3, field_stride=4, g=0.4,
+                      indirect=INDIRECT_FIELD, direct=DIRECT_LIGHT_VOLUME,
+                      field_precision=args.precision)
+    out = torch.empty((w.height, w.width, 3), dtype=torch.float32, device="cuda:0")
+    for i in range(args.frames):
+        ctx.render_frame(cam, rc, out)
+        torch.cuda.synchronize()
+        print(f"frame {i} done", flush=True)
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)  # 1 GiB read + 1 GiB write
+    torch.cuda.synchronize()
+    print("calibration copy done (1 GiB)", flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
