@@ -24,10 +24,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "march_kernel_c2_1080p_f16_hbm_traffic.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the field render kernel, taken from
+    the committed counter summary, or None when the kernel sources have changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            line = next(l for l in f if l.startswith("traffic-record:"))
+    except (OSError, StopIteration):
+        return None
+    rec = json.loads(line.split(":", 1)[1])
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2304_07338_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return int(rec["fetch_bytes"]) + int(rec["write_bytes"])
 
 
 def main():
@@ -174,7 +194,8 @@ def main():
         "march_steps_per_frame": int(steps_f),
         "cache_gather_fps": round(1000.0 / cache_ms, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": measured_traffic() if args.precision == "f16" else None,
                      "kernel": "march_kernel", "kernel_ms": round(kern_ms, 4),
                      "algorithmic_bytes_per_launch": int(bytes_frame)},
         "trace": {"photons": n_photons, "seconds": round(trace_s, 3),
