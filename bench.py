@@ -60,11 +60,24 @@ def main():
     ap.add_argument("--precision", default="f16", choices=["f16", "bf16", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=80, help="lattice side of the oracle sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-job launch")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--matched-rmse", action="store_true",
+                    help="run the large-scale comparison with the path tracer instead")
+    ap.add_argument("--mr-n", type=int, default=1024, help="volume side of the comparison")
+    ap.add_argument("--mr-width", type=int, default=1920)
+    ap.add_argument("--mr-height", type=int, default=1080)
+    ap.add_argument("--mr-ref-spp", type=int, default=4096)
+    ap.add_argument("--mr-photons", type=int, default=24, help="log2 photons per re-trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+
+    if args.matched_rmse:
+        print(json.dumps(matched_rmse(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -205,11 +218,211 @@ def main():
         "image_mean": img_mean,
     }
 
+    if not args.no_batch:
+        result["batch"] = batch_bench(args)
+
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(args, w, vol, tf, la, ctx, cam, fcfg, rc)
 
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def batch_bench(args):
+    """Batched launch: 64 uneven renders (16 views with sides in [256, 1024] x 4 single-light
+    field slots, each job at its own g) of the 256^3 f32 volume in one launch.  The autotuner
+    picks tile shape, block arrangement and launch mode; the timed launches replay the captured
+    HIP graph.  The four fields keep their initial parameters: the work of a frame (steps, field
+    queries, gathers and matrix-core tiles) does not depend on the parameter values."""
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import Context, FieldConfig, INDIRECT_FIELD
+    w = wl.C3
+    vol, tf, lights = wl.make_scene(w, device="cuda:0")
+    ctx = Context(0)
+    ctx.set_volume(vol.contiguous())
+    ctx.set_transfer_function(tf, w.extinction)
+    ctx.set_lights(sg.lights_array(lights))
+    ctx.build_light_volume(0.5)
+    for l in range(w.n_lights):
+        ctx.field_select(l)
+        ctx.field_init(FieldConfig(), seed=100 + l)
+    cams, cfgs = wl.batch_jobs(w)
+    for c in cfgs:
+        c.indirect = INDIRECT_FIELD
+        c.field_precision = args.precision
+    outs = [torch.empty((c.height, c.width, 3), dtype=torch.float32, device="cuda:0") for c in cams]
+    pixels = sum(c.width * c.height for c in cams)
+    t0 = time.time()
+    best = ctx.autotune_batch(cams, cfgs, outs, iters=1)
+    tune_s = time.time() - t0
+    ctx.set_tile_config(best["tile_w"], best["block_w"], best["block_h"])
+    ctx.set_launch_mode(best["persistent"], True)
+    for _ in range(2):
+        ctx.render_batch(cams, cfgs, outs)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.batch_steps):
+        ctx.render_batch(cams, cfgs, outs)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - ts) * 1000.0 / args.batch_steps
+    # the same 64 renders as separate launches (default tiles, no graph), for comparison
+    ctx.set_launch_mode(0, False)
+    ctx.set_tile_config(8, 2, 2)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for c, f, o in zip(cams, cfgs, outs):
+        ctx.render_frame(c, f, o)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - ts) * 1000.0
+    ctx.close()
+    log(f"[batch] 64 jobs, {pixels} pixels: {batch_ms:.2f} ms per batch launch, "
+        f"{single_ms:.2f} ms as 64 launches; autotuner {best} in {tune_s:.1f}s")
+    return {"workload": w.name, "jobs": len(cams), "pixels": pixels,
+            "ms_per_batch": round(batch_ms, 4), "jobs_per_s": round(len(cams) * 1000.0 / batch_ms, 2),
+            "pixels_per_s": round(pixels * 1000.0 / batch_ms, 1),
+            "ms_as_separate_launches": round(single_ms, 4),
+            "autotuned": {k: best[k] for k in ("tile_w", "block_w", "block_h", "persistent")},
+            "autotune_s": round(tune_s, 2), "graph": True,
+            "fields": "4 single-light fields at their initial parameters"}
+
+
+def matched_rmse(args):
+    """Large-scale comparison on one GPU: the photon-field render against a Monte Carlo path
+    tracer (8 bounces, HG sampling, Russian roulette from bounce 3) at equal error.
+
+    Scene: 1024^3 f16 (256 blobs, 6 octaves), 3 lights.  Two edits (a new transfer function,
+    then a moved light) each re-trace 2^24 photons into a 128^3 x 5-bin cache and retrain the
+    field with the cache-and-train recipe; the edit-to-first-frame latency covers light volume,
+    trace, training and the first frame.  On the final scene: the field render (4 spp, field
+    every 4 steps, light-transmittance volume, FP16 matrix cores) and the plain cache gather at
+    g = 0.4 (a trained bin) and 0.2 (between bins), and the path tracer at 16..256 spp, each
+    judged against a path-traced reference at --mr-ref-spp.  The path tracer's error is fitted
+    as c^2 (1/spp + 1/ref_spp) (its own noise plus the reference's), solved for the spp at which
+    it equals the field's error, and its time interpolated there."""
+    import numpy as np
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import (Context, FieldConfig, RenderConfig, TrainConfig,
+                                          DIRECT_LIGHT_VOLUME, INDIRECT_CACHE, INDIRECT_FIELD)
+    w = wl.C4
+    W, H = args.mr_width, args.mr_height
+    n = args.mr_n
+    t0 = time.time()
+    vol, tf, lights = wl.make_scene(w, device="cuda:0", n=n)
+    torch.cuda.synchronize()
+    log(f"[mr] volume {n}^3 {w.vol_dtype} in {time.time() - t0:.1f}s")
+    ctx = Context(0)
+    ctx.set_volume(vol.contiguous())
+    del vol
+    la = sg.lights_array(lights)
+    cam = wl.camera(w, 0, W, H)
+    steps_cap = int(math.ceil(n * math.sqrt(3.0) * 2.0))
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda:0")
+
+    def field_rc(g, indirect=INDIRECT_FIELD):
+        return RenderConfig(spp=4, step_voxels=0.5, max_steps=steps_cap, t_min=1e-3,
+                            field_stride=4, g=g, indirect=indirect, direct=DIRECT_LIGHT_VOLUME,
+                            field_precision="f16", field_slot=0, seed=3)
+
+    def rebuild(tf_table, lights_arr, seed):
+        """set the scene, rebuild every derived quantity and render the first frame"""
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ctx.set_transfer_function(tf_table, w.extinction)
+        ctx.set_lights(lights_arr)
+        ctx.build_light_volume(0.5)
+        st = ctx.trace_photon_cache(1 << args.mr_photons, wl.C1_G_BINS, cache_res=128,
+                                    seed=seed, max_collisions=8, rr_start=3)
+        ctx.field_init(FieldConfig(), seed=seed)
+        hist = ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, seed=seed))
+        ctx.render_frame(cam, field_rc(0.4), out)
+        torch.cuda.synchronize()
+        return time.perf_counter() - ts, st, float(np.mean(hist[-20:]))
+
+    lat0, st, loss = rebuild(tf, la, 11)
+    log(f"[mr] initial build + first frame {lat0:.2f}s ({st['n_records']} records, loss {loss:.4g})")
+    tf2 = sg.make_transfer_function(w.seed + 17)
+    lat_tf, _, loss = rebuild(tf2, la, 12)
+    log(f"[mr] transfer-function edit -> first frame {lat_tf:.2f}s (loss {loss:.4g})")
+    la2 = la.copy()
+    moved = sg.make_lights(1, w.seed + 29)[0]
+    la2[0, :3] = moved.pos
+    lat_light, _, loss = rebuild(tf2, la2, 13)
+    log(f"[mr] light edit -> first frame {lat_light:.2f}s (loss {loss:.4g})")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ts) * 1000.0 / reps
+
+    per_g = {}
+    pt_spp = [16, 32, 64, 128, 256]
+    for g in (0.4, 0.2):
+        ref = ctx.render_path_traced(cam, args.mr_ref_spp, max_bounces=8, g=g, rr_start=3,
+                                     seed=1000)
+        torch.cuda.synchronize()
+        field_ms = timed(lambda: ctx.render_frame(cam, field_rc(g), out), 3)
+        e_field = ctx.image_error(out, ref)
+        cache_ms = timed(lambda: ctx.render_frame(cam, field_rc(g, INDIRECT_CACHE), out), 3)
+        e_cache = ctx.image_error(out, ref)
+        pts = []
+        for spp in pt_spp:
+            img = torch.empty_like(out)
+            ms = timed(lambda: ctx.render_path_traced(cam, spp, max_bounces=8, g=g, rr_start=3,
+                                                      seed=2000 + spp, out=img), 1)
+            pts.append((spp, ms, ctx.image_error(img, ref)[0]))
+            log(f"[mr] g={g} PT {spp} spp: {ms:.1f} ms, RMSE {pts[-1][2]:.4g}")
+        spp_a = np.array([p[0] for p in pts], dtype=np.float64)
+        t_a = np.array([p[1] for p in pts])
+        e_a = np.array([p[2] for p in pts])
+        basis = 1.0 / spp_a + 1.0 / args.mr_ref_spp
+        c2 = float(np.sum(e_a ** 2 * basis) / np.sum(basis ** 2))
+        slope, icpt = np.polyfit(spp_a, t_a, 1)
+        inv = e_field[0] ** 2 / c2 - 1.0 / args.mr_ref_spp
+        if inv <= 0:
+            spp_star, note = None, "field error below the reference's own noise level"
+            speedup = None
+        else:
+            spp_star = 1.0 / inv
+            note = ("interpolated" if pt_spp[0] <= spp_star <= pt_spp[-1] else
+                    "extrapolated: the field is more accurate than the path tracer at 256 spp"
+                    if spp_star > pt_spp[-1] else
+                    "the path tracer reaches the field's error below 16 spp")
+            t_star = max(icpt + slope * spp_star, 0.0)
+            speedup = t_star / field_ms
+        per_g[str(g)] = {
+            "field": {"ms": round(field_ms, 3), "rmse": e_field[0], "rel_rmse": e_field[1],
+                      "psnr": e_field[2]},
+            "cache_gather": {"ms": round(cache_ms, 3), "rmse": e_cache[0], "rel_rmse": e_cache[1],
+                             "psnr": e_cache[2]},
+            "path_tracer": [{"spp": p[0], "ms": round(p[1], 3), "rmse": p[2]} for p in pts],
+            "pt_noise_c": math.sqrt(c2), "spp_matched": spp_star, "note": note,
+            "speedup_at_matched_rmse": speedup}
+        log(f"[mr] g={g}: field {field_ms:.1f} ms RMSE {e_field[0]:.4g}; cache {cache_ms:.1f} ms "
+            f"RMSE {e_cache[0]:.4g}; matched spp {spp_star} ({note}), speedup {speedup}")
+    ctx.close()
+    sp = per_g["0.4"]["speedup_at_matched_rmse"]
+    return {
+        "metric": "photon field vs path tracer at matched RMSE (time ratio)",
+        "value": round(sp, 3) if sp is not None else None, "unit": "x", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "f16-mfma/f32",
+        "data": "synthetic",
+        "config": {"workload": w.name if n == w.n and (W, H) == (1920, 1080) else
+                   f"{w.name} at {n}^3, {W}x{H}", "volume": f"{n}^3 f16", "resolution": f"{W}x{H}",
+                   "field_spp": 4, "max_steps": steps_cap, "pt_spp": pt_spp,
+                   "reference_spp": args.mr_ref_spp, "photons_per_trace": 1 << args.mr_photons,
+                   "train_steps": args.train_steps},
+        "edit_to_first_frame_s": {"initial": round(lat0, 3), "transfer_function": round(lat_tf, 3),
+                                  "light": round(lat_light, 3)},
+        "per_g": per_g,
+    }
 
 
 def cpu_baseline(args, w, vol, tf, la, ctx, cam, fcfg, rc):

@@ -51,3 +51,26 @@ def make_scene(w: Workload, device: str = "cpu", n: Optional[int] = None):
 
 def camera(w: Workload, index: int = 0, width: Optional[int] = None, height: Optional[int] = None):
     return sg.make_camera(w.seed, index, width or w.width, height or w.height)
+
+
+def batch_jobs(w: Workload = C3, n_cameras: int = 16, side_lo: int = 256, side_hi: int = 1024):
+    """The batched-launch workload: n_cameras seeded views with width and height each drawn
+    uniformly from {side_lo..side_hi}, times one job per light of the scene.  Job i of light l
+    lights the volume with light l only, reads field slot l (one single-light field per light
+    position) and takes its own g ~ U[-0.9, 0.9].  Returns (cameras, render configs) without
+    the indirect mode, which the caller sets."""
+    import numpy as np
+    from .pfn import RenderConfig, DIRECT_LIGHT_VOLUME
+    r = np.random.default_rng([int(w.seed), sg.SUB_CAMERAS, 7919])
+    sides = r.integers(side_lo, side_hi + 1, size=(n_cameras, 2))
+    g = sg.uniform_g(w.seed, n_cameras * w.n_lights)
+    cams, cfgs = [], []
+    for c in range(n_cameras):
+        cam = sg.make_camera(w.seed, c, int(sides[c, 0]), int(sides[c, 1]))
+        for l in range(w.n_lights):
+            k = c * w.n_lights + l
+            cams.append(cam)
+            cfgs.append(RenderConfig(spp=1, step_voxels=0.5, max_steps=1024, t_min=1e-3,
+                                     field_stride=4, g=float(g[k]), direct=DIRECT_LIGHT_VOLUME,
+                                     light_mask=1 << l, field_slot=l, seed=k))
+    return cams, cfgs
