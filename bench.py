@@ -24,23 +24,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "march_kernel_c2_1080p_f16_hbm_traffic.md")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the field render kernel, taken from
-    the committed counter summary, or None when the kernel sources have changed since."""
+def measured_traffic(kernel):
+    """Calibrated FETCH_SIZE + WRITE_SIZE bytes per frame of `kernel` (all its launches of one
+    frame), taken from the committed counter summaries, or None when there is none for it or the
+    kernel sources have changed since."""
+    import glob
     import hashlib
-    try:
-        with open(TRAFFIC_PROFILE) as f:
-            line = next(l for l in f if l.startswith("traffic-record:"))
-    except (OSError, StopIteration):
+    rec = None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.md"))):
+        with open(path) as f:
+            for l in f:
+                if l.startswith("traffic-record:"):
+                    r = json.loads(l.split(":", 1)[1])
+                    if r["kernel"].split("<")[0] == kernel:
+                        rec = r
+    if rec is None:
         return None
-    rec = json.loads(line.split(":", 1)[1])
     h = hashlib.sha256()
     for name in rec["sources"]:
         with open(os.path.join(ROOT, "paper_2304_07338_amd", "csrc", name), "rb") as f:
@@ -61,6 +66,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=80, help="lattice side of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-job launch")
+    ap.add_argument("--strategy", default="auto", choices=["auto", "fused", "wavefront"],
+                    help="form of the field-lit render")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--matched-rmse", action="store_true",
                     help="run the large-scale comparison with the path tracer instead")
@@ -97,6 +104,7 @@ def main():
     torch.cuda.synchronize()
     log(f"[setup] volume {w.n}^3 {w.vol_dtype} generated in {time.time() - t0:.1f}s")
     ctx = Context(0)
+    ctx.set_render_strategy(args.strategy)
     ctx.set_volume(vol.contiguous())
     ctx.set_transfer_function(tf, w.extinction)
     ctx.set_lights(la)
@@ -160,18 +168,47 @@ def main():
     torch.cuda.synchronize()
     te = time.perf_counter()
     march_ms, launches = ctx.timing_get(_ffi.TK_MARCH)
+    ktimes = {k: ctx.timing_get(i) for k, i in (("wf_march_kernel", _ffi.TK_WF_MARCH),
+                                                 ("wf_encode_kernel", _ffi.TK_WF_ENCODE),
+                                                 ("wf_field_kernel", _ffi.TK_WF_FIELD),
+                                                 ("wf_resolve_kernel", _ffi.TK_WF_RESOLVE))}
     ctx.timing_enable(False)
     ms_per_step = (te - ts) * 1000.0 / args.steps
-    kern_ms = march_ms / max(launches, 1)
+    frame_ms = march_ms / max(launches, 1)
     fps = 1000.0 / ms_per_step
     img_mean = float(out.mean())
 
-    # algorithmic bytes of one frame: per step 8 density corners (f16) + 8 light-volume texels
-    # (4 x f16); per field query 16 levels x (8 + 4) corners x 2 features x 2 bytes
+    # algorithmic bytes of one frame: per step 8 density corners + 8 light-volume texels
+    # (4 x f16); per field query 16 levels x (8 + 4) corners x 2 features
     vbytes = 2 if w.vol_dtype == "f16" else 4
     feat_bytes = {"f16": 4, "bf16": 4, "f32": 8}[args.precision]
-    bytes_frame = steps_f * (8 * vbytes + 8 * 8) + queries_f * 16 * 12 * feat_bytes
-    achieved = bytes_frame / (kern_ms * 1e-3) / 1e9
+    step_bytes = 8 * vbytes + 8 * 8
+    bytes_frame = steps_f * step_bytes + queries_f * 16 * 12 * feat_bytes
+    mlp_flop = 2 * (65 * 64 + 64 * 64 * 2 + 64 * 3)  # 3 hidden layers of 64, FLOP per query
+    kernels = {}
+    if ktimes["wf_march_kernel"][1] > 0:
+        # wavefront form: per kernel, per frame
+        n_groups = 1 + 7  # coarse levels together, then each fine hashed level (C1 field)
+        per = {"wf_march_kernel": (steps_f * step_bytes + queries_f * 24, 0),
+               "wf_encode_kernel": (queries_f * (16 * 8 * feat_bytes + 16 * feat_bytes
+                                                 + 12 * n_groups), 0),
+               "wf_field_kernel": (queries_f * (16 * feat_bytes + 12), queries_f * mlp_flop),
+               "wf_resolve_kernel": (0, 0)}
+        for k, (ms, n) in ktimes.items():
+            kms = ms / args.steps
+            b, fl = per[k]
+            kernels[k] = {"ms_per_frame": round(kms, 4), "launches_per_frame": n / args.steps,
+                          "algorithmic_bytes_per_frame": int(b),
+                          "GB_s": round(b / (kms * 1e-3) / 1e9, 2) if kms > 0 else None}
+            if fl:
+                kernels[k]["TFLOP_s"] = round(fl / (kms * 1e-3) / 1e12, 3)
+        dom = max((k for k in kernels if k != "wf_resolve_kernel"),
+                  key=lambda k: kernels[k]["ms_per_frame"])
+        dom_bytes = kernels[dom]["algorithmic_bytes_per_frame"]
+        dom_ms = kernels[dom]["ms_per_frame"]
+    else:
+        dom, dom_bytes, dom_ms = "march_kernel", bytes_frame, frame_ms
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
 
     # plain cache gather render of the same frame (no network)
     rc_cache = RenderConfig(**{**rc.__dict__, "indirect": INDIRECT_CACHE})
@@ -208,9 +245,12 @@ def main():
         "cache_gather_fps": round(1000.0 / cache_ms, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic() if args.precision == "f16" else None,
-                     "kernel": "march_kernel", "kernel_ms": round(kern_ms, 4),
-                     "algorithmic_bytes_per_launch": int(bytes_frame)},
+                     "traffic": measured_traffic(dom) if args.precision == "f16" else None,
+                     "kernel": dom, "kernel_ms_per_frame": round(dom_ms, 4),
+                     "algorithmic_bytes_per_frame": int(dom_bytes)},
+        "frame": {"gpu_ms": round(frame_ms, 4), "algorithmic_bytes": int(bytes_frame),
+                  "GB_s": round(bytes_frame / (frame_ms * 1e-3) / 1e9, 2),
+                  "strategy": "wavefront" if kernels else "fused", "kernels": kernels},
         "trace": {"photons": n_photons, "seconds": round(trace_s, 3),
                   "kernel_ms": round(trace_ms, 3),
                   "photons_per_s": round(n_photons / (trace_ms * 1e-3), 1) if trace_ms else None},

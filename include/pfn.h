@@ -236,6 +236,19 @@ pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int bl
  * jobs are done.  use_graph != 0 captures each distinct launch into a HIP graph on first use and
  * replays it afterwards (the job table is refreshed before every replay). */
 pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_graph);
+/* How field-lit frames are rendered (Section 3.6 ray marcher, both forms give the same pixels up
+ * to the order of FP32 additions):
+ *   PFN_STRATEGY_FUSED: one kernel marches, evaluates the field on the matrix cores inside the
+ *     march loop and composites (the only form the persistent and graph launches use);
+ *   PFN_STRATEGY_WAVEFRONT: rounds of a march kernel that stores up to 16 field queries per ray,
+ *     level-major position-encoding kernels (each fine hashed level alone, so that its table
+ *     stays in L2) and a matrix-core field kernel per 16-query ray tile; needs every job of the
+ *     call to read one field slot and no graph capture, else the fused kernel runs;
+ *   PFN_STRATEGY_AUTO (default): the wavefront form wherever it applies.
+ * Device buffers of the wavefront form (about 1.5 KB per ray of a round, at most 2^21 rays per
+ * round, plus 12 B per ray sample of the frame) are kept in the context and grown on demand. */
+typedef enum { PFN_STRATEGY_AUTO = 0, PFN_STRATEGY_FUSED = 1, PFN_STRATEGY_WAVEFRONT = 2 } pfn_strategy;
+pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy);
 /* Autotuner: time every tile shape / block arrangement / launch mode on this batch (iters
  * launches each), keep the fastest for the context and return it (cached per batch shape). */
 pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs,
@@ -245,8 +258,10 @@ pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs,
 /* ------------------------------------------------------------------ timing */
 /* When enabled, the main kernels are bracketed by HIP events on the stream they run on; the
  * accumulated device time (ms) and launch count per kernel are returned by pfn_timing_get.
- * kernel: 0 = ray march, 1 = photon trace, 2 = training step (fused forward/backward),
- * 3 = path tracer, 4 = field query, 5 = Adam. */
+ * kernel: 0 = ray march (a whole frame or batch, every kernel of it), 1 = photon trace,
+ * 2 = training step (fused forward/backward), 3 = path tracer, 4 = field query, 5 = Adam;
+ * kernels of the wavefront render: 6 = march rounds, 7 = position-encoding launches,
+ * 8 = matrix-core field tiles, 9 = pixel resolve.  Ids 0..15 are valid. */
 pfn_status pfn_timing_enable(pfn_context *ctx, int on);
 pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);
 pfn_status pfn_timing_reset(pfn_context *ctx);

@@ -15,6 +15,7 @@ PFN_F32, PFN_F16, PFN_BF16 = 0, 1, 2
 INDIRECT_NONE, INDIRECT_CACHE, INDIRECT_FIELD = 0, 1, 2
 DIRECT_SHADOW_RAYS, DIRECT_LIGHT_VOLUME = 0, 1
 TK_MARCH, TK_TRACE, TK_TRAIN, TK_PT, TK_QUERY, TK_ADAM = 0, 1, 2, 3, 4, 5
+TK_WF_MARCH, TK_WF_ENCODE, TK_WF_FIELD, TK_WF_RESOLVE = 6, 7, 8, 9
 
 
 class PointLight(C.Structure):
@@ -104,6 +105,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "pfn_set_tile_config": (C.c_int, [ctxp, C.c_int, C.c_int, C.c_int]),
     "pfn_set_launch_mode": (C.c_int, [ctxp, C.c_int, C.c_int]),
+    "pfn_set_render_strategy": (C.c_int, [ctxp, C.c_int]),
     "pfn_autotune_batch": (C.c_int, [ctxp, C.POINTER(RenderJob), C.c_int, C.c_int,
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_double)]),

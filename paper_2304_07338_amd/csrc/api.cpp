@@ -48,10 +48,13 @@ pfn_status ensure_scratch(pfn_context *ctx, size_t bytes) {
   return PFN_OK;
 }
 
+// Pending event pairs are collected once none is open (when the totals are read, or when the
+// pool is full at the next opening).
 static void timing_collect(pfn_context *ctx) {
+  if (ctx->ev_open > 0) return;
   for (int i = 0; i < ctx->ev_pending; ++i) {
     hipEvent_t a = ctx->ev_pool[2 * i], b = ctx->ev_pool[2 * i + 1];
-    if (hipEventSynchronize(b) != hipSuccess) continue;
+    if (ctx->ev_kernel[i] < 0 || hipEventSynchronize(b) != hipSuccess) continue;
     float ms = 0.0f;
     if (hipEventElapsedTime(&ms, a, b) == hipSuccess) {
       ctx->t_ms[ctx->ev_kernel[i]] += ms;
@@ -61,26 +64,30 @@ static void timing_collect(pfn_context *ctx) {
   ctx->ev_pending = 0;
 }
 
-// Event pair around one launch on the launch's stream; the host does not wait here.
-void timing_begin(pfn_context *ctx) {
-  if (!ctx->timing) return;
-  if (ctx->ev_pending >= 256) timing_collect(ctx);
+// Opens an event pair on the context's stream before a launch; the host does not wait here.
+// Returns the pair's slot (-1 when timing is off); pairs may nest.
+int timing_begin(pfn_context *ctx) {
+  if (!ctx->timing) return -1;
+  if (ctx->ev_pending >= 512) timing_collect(ctx);
   int i = ctx->ev_pending;
   while ((int)ctx->ev_pool.size() < 2 * (i + 1)) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventCreate(&e) != hipSuccess) return -1;
     ctx->ev_pool.push_back(e);
-    ctx->ev_kernel.push_back(0);
+    if (ctx->ev_kernel.size() * 2 < ctx->ev_pool.size()) ctx->ev_kernel.push_back(-1);
   }
-  (void)hipEventRecord(ctx->ev_pool[2 * i], ctx->stream);
-}
-void timing_end(pfn_context *ctx, int kernel) {
-  if (!ctx->timing) return;
-  int i = ctx->ev_pending;
-  if ((int)ctx->ev_pool.size() < 2 * (i + 1)) return;
-  (void)hipEventRecord(ctx->ev_pool[2 * i + 1], ctx->stream);
-  ctx->ev_kernel[i] = kernel;
+  if (hipEventRecord(ctx->ev_pool[2 * i], ctx->stream) != hipSuccess) return -1;
+  ctx->ev_kernel[i] = -1;
   ctx->ev_pending = i + 1;
+  ctx->ev_open += 1;
+  return i;
+}
+
+void timing_end(pfn_context *ctx, int slot, int kernel) {
+  if (slot < 0 || !ctx->timing) return;
+  (void)hipEventRecord(ctx->ev_pool[2 * slot + 1], ctx->stream);
+  ctx->ev_kernel[slot] = kernel;
+  ctx->ev_open -= 1;
 }
 
 static bool finite3(const float *v) {
@@ -141,6 +148,7 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   dev_free(ctx->mlp_ptrs_dev);
   dev_free(ctx->counters);
   dev_free(ctx->queues);
+  wf_release(ctx->wf);
   for (auto &g : ctx->graphs) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -487,9 +495,9 @@ extern "C" pfn_status pfn_field_query(pfn_context *ctx, pfn_dtype precision, con
   int p = prec_of(precision);
   st = field_refresh(ctx, f, p);
   if (st) return st;
-  timing_begin(ctx);
+  const int tslot = timing_begin(ctx);
   PFN_HIP(ctx, launch_field_query(ctx, f, p, xyz, dir, g, n, lp, rgb));
-  timing_end(ctx, TK_QUERY);
+  timing_end(ctx, tslot, TK_QUERY);
   return PFN_OK;
 }
 
@@ -591,6 +599,9 @@ static void fill_job(pfn_context *ctx, const pfn_camera *c, const pfn_render_par
   }
   int bw = tc.tile_w * tc.block_w, bh = tc.tile_h * tc.block_h;
   j.blocks_x = (c->width + bw - 1) / bw;
+  j.tiles_x = (c->width + tc.tile_w - 1) / tc.tile_w;
+  j.tiles = j.tiles_x * ((c->height + tc.tile_h - 1) / tc.tile_h);
+  j.ray_begin = 0;
 }
 
 pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc) {
@@ -681,7 +692,16 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
     PFN_HIP(ctx, hipMemsetAsync(ctx->counters, 0, 16, ctx->stream));
     a.counters = ctx->counters;
   }
-  if (ctx->use_graph) {
+  int wf_slot = -1;
+  if (p0.indirect == PFN_INDIRECT_FIELD && !ctx->use_graph && ctx->strategy != PFN_STRATEGY_FUSED) {
+    wf_slot = jobs[0].params.field_slot;
+    for (int i = 1; i < n_jobs; ++i)
+      if (jobs[i].params.field_slot != wf_slot) wf_slot = -1;
+  }
+  if (wf_slot >= 0) {
+    pfn_status st = run_wavefront(ctx, a, mj, p0.direct, prec, wf_slot, fd[wf_slot]);
+    if (st) return st;
+  } else if (ctx->use_graph) {
     // replay a captured launch with the same arguments (the job table, field descriptors and
     // weight pointers it reads were refreshed above); capture it on first use
     std::vector<unsigned char> key(sizeof(MarchArgs) + 4 * sizeof(int));
@@ -710,13 +730,13 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
       ctx->graphs.push_back(ng);
       g = &ctx->graphs.back();
     }
-    timing_begin(ctx);
+    const int tslot = timing_begin(ctx);
     PFN_HIP(ctx, hipGraphLaunch(g->exec, ctx->stream));
-    timing_end(ctx, TK_MARCH);
+    timing_end(ctx, tslot, TK_MARCH);
   } else {
-    timing_begin(ctx);
+    const int tslot = timing_begin(ctx);
     PFN_HIP(ctx, launch_march(a, ctx->vol_dtype, p0.direct, p0.indirect, prec, ctx->stream));
-    timing_end(ctx, TK_MARCH);
+    timing_end(ctx, tslot, TK_MARCH);
   }
   if (ctx->counting) {
     PFN_HIP(ctx, hipMemcpyAsync(ctx->last_counts, ctx->counters, 16, hipMemcpyDeviceToHost,
@@ -770,7 +790,7 @@ extern "C" pfn_status pfn_timing_enable(pfn_context *ctx, int on) {
 
 extern "C" pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *ms, int64_t *launches) {
   CHECK_CTX(ctx);
-  ARG(kernel >= 0 && kernel < 8, "kernel id in [0, 8)");
+  ARG(kernel >= 0 && kernel < PFN_TIMED_KERNELS, "kernel id in [0, 16)");
   timing_collect(ctx);
   if (ms) *ms = ctx->t_ms[kernel];
   if (launches) *launches = ctx->t_n[kernel];
@@ -780,10 +800,19 @@ extern "C" pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *ms, i
 extern "C" pfn_status pfn_timing_reset(pfn_context *ctx) {
   CHECK_CTX(ctx);
   timing_collect(ctx);
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < PFN_TIMED_KERNELS; ++i) {
     ctx->t_ms[i] = 0.0;
     ctx->t_n[i] = 0;
   }
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy) {
+  CHECK_CTX(ctx);
+  ARG(strategy == PFN_STRATEGY_AUTO || strategy == PFN_STRATEGY_FUSED ||
+          strategy == PFN_STRATEGY_WAVEFRONT,
+      "strategy is PFN_STRATEGY_AUTO, PFN_STRATEGY_FUSED or PFN_STRATEGY_WAVEFRONT");
+  ctx->strategy = strategy;
   return PFN_OK;
 }
 

@@ -8,6 +8,8 @@
 #include "pfn_device.h"
 #include "pfn_field_dev.h"
 
+#define PFN_MAX_LIGHTS 4
+
 // One frame of a (batched) render.  right/up are pre-scaled by tan(fov/2)*aspect and tan(fov/2).
 struct MarchJob {
   float eye[3], fwd[3], right[3], up[3];
@@ -18,6 +20,10 @@ struct MarchJob {
   uint64_t seed;
   float *out;
   int block_begin, blocks_x;
+  // wavefront launch: rays of this job are [ray_begin, ray_begin + spp * tiles * 64), sample
+  // major, then 64-pixel tiles in row-major tile order, then lanes inside the tile
+  int64_t ray_begin;
+  int tiles_x, tiles;
 };
 
 struct MarchArgs {
@@ -26,7 +32,7 @@ struct MarchArgs {
   const float4 *tf;
   float ext_scale;
   int n_lights;
-  float light_pos[4][3], light_int[4][3];
+  float light_pos[PFN_MAX_LIGHTS][3], light_int[PFN_MAX_LIGHTS][3];
   const ushort4 *lightvol;
   BrickGrid lvg;
   const float4 *cache;

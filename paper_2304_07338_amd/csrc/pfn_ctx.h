@@ -13,7 +13,6 @@
 #include "pfn_device.h"
 #include "pfn_field_dev.h"
 
-#define PFN_MAX_LIGHTS 4
 #define PFN_MAX_FIELDS 8
 
 struct FieldSlot {
@@ -46,6 +45,25 @@ struct MarchGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
+
+// Buffers of the wavefront render (rays per round, query slots, features, per-ray sums).
+struct WfState {
+  uint32_t *list_ray[2] = {nullptr, nullptr};  // continuing rays, ping-pong between rounds
+  int *list_j[2] = {nullptr, nullptr};
+  float *list_T[2] = {nullptr, nullptr};
+  uint32_t *ent_ray = nullptr;
+  int *ent_cnt = nullptr;
+  float2 *ent_u = nullptr;
+  float *slot[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // x y z, W rgb
+  void *feat = nullptr;
+  float *acc = nullptr;
+  unsigned *count = nullptr;       // device counter of continuing rays
+  unsigned *host_count = nullptr;  // pinned copy
+  int64_t *pix_begin = nullptr;
+  size_t pix_cap = 0, ent_cap = 0, feat_elem = 0, acc_cap = 0;
+};
+
+#define PFN_TIMED_KERNELS 16
 
 struct pfn_context {
   int device = 0;
@@ -101,6 +119,8 @@ struct pfn_context {
   hipStream_t cap_stream = nullptr;
   std::vector<MarchGraph> graphs;
   std::vector<std::pair<std::vector<unsigned char>, TileConfig>> tuned;  // autotuner cache
+  int strategy = PFN_STRATEGY_AUTO;  // field renders: fused kernel or wavefront rounds
+  WfState wf;
 
   // training activations / deltas (neuron-major, 16-bit or FP32)
   void *train_act = nullptr;
@@ -120,11 +140,15 @@ struct pfn_context {
   std::vector<hipEvent_t> ev_pool;      // 2 events per slot
   std::vector<int> ev_kernel;           // kernel id of each pending slot
   int ev_pending = 0;
-  double t_ms[8] = {};
-  int64_t t_n[8] = {};
+  int ev_open = 0;
+  double t_ms[PFN_TIMED_KERNELS] = {};
+  int64_t t_n[PFN_TIMED_KERNELS] = {};
 };
 
-enum TimedKernel { TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5 };
+enum TimedKernel {
+  TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5,
+  TK_WF_MARCH = 6, TK_WF_ENCODE = 7, TK_WF_FIELD = 8, TK_WF_RESOLVE = 9
+};
 
 // Error helpers
 pfn_status pfn_fail(pfn_context *ctx, pfn_status st, const std::string &msg);
@@ -136,8 +160,11 @@ pfn_status pfn_hip(pfn_context *ctx, hipError_t e, const char *what);
   } while (0)
 
 pfn_status ensure_scratch(pfn_context *ctx, size_t bytes);
-void timing_begin(pfn_context *ctx);
-void timing_end(pfn_context *ctx, int kernel);
+pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
+                         int direct, int prec, int slot, const FieldDev &fd_host);
+void wf_release(WfState &w);
+int timing_begin(pfn_context *ctx);
+void timing_end(pfn_context *ctx, int slot, int kernel);
 
 // Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,

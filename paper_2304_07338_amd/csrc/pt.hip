@@ -181,7 +181,7 @@ extern "C" pfn_status pfn_render_path_traced(pfn_context *ctx, const pfn_camera 
   // keep each launch to about 2^27 pixel-samples
   int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(spp, ((int64_t)1 << 27) / npix));
   unsigned blocks = (unsigned)((npix + PT_THREADS - 1) / PT_THREADS);
-  timing_begin(ctx);
+  const int tslot = timing_begin(ctx);
   for (int s0 = 0; s0 < spp; s0 += chunk) {
     a.s_begin = s0;
     a.s_end = std::min(spp, s0 + chunk);
@@ -193,7 +193,7 @@ extern "C" pfn_status pfn_render_path_traced(pfn_context *ctx, const pfn_camera 
       hipLaunchKernelGGL(pt_kernel<float>, dim3(blocks), dim3(PT_THREADS), 0, ctx->stream, a);
     PFN_HIP(ctx, hipGetLastError());
   }
-  timing_end(ctx, TK_PT);
+  timing_end(ctx, tslot, TK_PT);
   return PFN_OK;
 }
 

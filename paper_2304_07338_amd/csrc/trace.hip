@@ -361,13 +361,13 @@ extern "C" pfn_status pfn_trace_photon_cache(pfn_context *ctx, const pfn_trace_p
   a.tally = tally;
   uint64_t want = (p->n_photons + TRACE_THREADS - 1) / TRACE_THREADS;
   unsigned blocks = (unsigned)(want < 256 * 32 ? want : 256 * 32);
-  timing_begin(ctx);
+  const int tslot = timing_begin(ctx);
   if (ctx->vol_dtype == PFN_F16)
     hipLaunchKernelGGL(trace_kernel<__half>, dim3(blocks), dim3(TRACE_THREADS), 0, ctx->stream, a);
   else
     hipLaunchKernelGGL(trace_kernel<float>, dim3(blocks), dim3(TRACE_THREADS), 0, ctx->stream, a);
   PFN_HIP(ctx, hipGetLastError());
-  timing_end(ctx, TK_TRACE);
+  timing_end(ctx, tslot, TK_TRACE);
   ctx->rec_photons = p->n_photons;
   ctx->rec_maxrec = maxrec;
 

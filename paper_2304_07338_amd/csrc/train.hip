@@ -739,10 +739,10 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
   a.loss = loss_dev;
   int64_t ntiles = tl.ldn / 16;
   unsigned blocks = (unsigned)((ntiles + 3) / 4);
-  timing_begin(ctx);
+  const int tslot = timing_begin(ctx);
   PFN_HIP(ctx, gen ? launch_fb<true>(a, prec, H, blocks, ctx->stream)
                    : launch_fb<false>(a, prec, H, blocks, ctx->stream));
-  timing_end(ctx, TK_TRAIN);
+  timing_end(ctx, tslot, TK_TRAIN);
   // weight gradients, one launch per layer
   const int kchunk = 2048;
   for (int m = 0; m <= H; ++m) {
@@ -785,10 +785,10 @@ static pfn_status run_adam(pfn_context *ctx, FieldSlot &f, float *grad, int64_t 
   a.lp16 = prec == P_F16 ? f.lp_table[P_F16] : nullptr;
   a.lpbf = prec == P_BF16 ? f.lp_table[P_BF16] : nullptr;
   size_t pairs = (f.n_params + 1) / 2;
-  timing_begin(ctx);
+  const int tslot = timing_begin(ctx);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((pairs + 255) / 256)), dim3(256), 0, ctx->stream, a);
   PFN_HIP(ctx, hipGetLastError());
-  timing_end(ctx, TK_ADAM);
+  timing_end(ctx, tslot, TK_ADAM);
   // The master changed: every derived copy is stale, except the 16-bit grid copy of the
   // training precision, which the Adam pass rewrote; its MLP image is repacked here.
   field_params_changed(f);

@@ -1,0 +1,622 @@
+// Wavefront form of the photon-field ray marcher (Section 3.6 with Eq. (3): the field supplies
+// L_i at the samples of a ray marcher).  The fused kernel keeps a ray and its field queries in
+// one wave; here the frame runs in rounds of four kernels so that each piece runs at its own
+// best occupancy and the fine hash levels of the position encoding stay resident in L2:
+//
+//   1. wf_march_kernel: one lane per ray (a pixel sample).  The lane marches groups of `stride`
+//      steps exactly as the fused kernel does (transfer function, transmittance, direct light,
+//      compositing) and, for every group with a non-zero weight W = sum T*alpha*albedo, stores
+//      the query (position of the group's first step, W) in the ray's next slot.  After
+//      WF_SLOTS queries the ray stops and is appended to the list of rays continued next round.
+//   2. wf_encode_kernel: the position encoding of every stored query, written level-major as
+//      the 16-bit (or FP32) features the matrix cores consume.  One launch covers the coarse
+//      levels; each fine hashed level (cells smaller than the spacing of neighbouring queries)
+//      gets a launch of its own so that its 2 MB table is the only grid table the L2 holds.
+//   3. wf_field_kernel: one wave per ray of the round: the direction encoding (shared by all
+//      queries of the ray), the MLP of its 16 queries on the matrix cores, the Eq. (7) decode,
+//      and the sum of W * L_i over the queries in a fixed order, added to the ray's sum.
+//   4. after the last round, wf_resolve_kernel averages each pixel's samples.
+//
+// Every ray's arithmetic is the fused kernel's; only the order in which the W * L_i terms are
+// added to the pixel differs.  Results do not depend on the lane or list position a ray gets,
+// so a frame is deterministic and a batch renders exactly as its jobs rendered alone.
+#include "march.h"
+#include "march_dev.h"
+#include "pfn_ctx.h"
+
+#define WF_THREADS 256
+#define WF_SLOTS 16                  // queries per ray per round: one matrix-core tile
+#define WF_MAX_ENTRIES (1 << 21)     // rays per round
+#define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
+
+struct WfArgs {
+  MarchArgs m;
+  // continuing rays of the previous round (entries [0, n_cont)) followed by fresh rays
+  const uint32_t *in_ray;
+  const int *in_j;
+  const float *in_T;
+  int n_cont, n_fresh;
+  int64_t fresh_begin;
+  uint32_t *out_ray;
+  int *out_j;
+  float *out_T;
+  unsigned *out_count;
+  // per entry of this round
+  uint32_t *ent_ray;
+  int *ent_cnt;
+  float2 *ent_u;
+  // per query slot (entry * WF_SLOTS + k)
+  float *qx, *qy, *qz, *wr, *wg, *wb;
+  float *acc;  // per ray: RGB sum of the sample
+};
+
+struct WfEncArgs {
+  const FieldDev *F;
+  const int *ent_cnt;
+  const float *qx, *qy, *qz;
+  void *feat;           // [level][slot]: uint32 (two 16-bit features) or float2 (FP32)
+  int64_t n_slots;
+  int l0, l1;
+};
+
+struct WfFieldArgs {
+  const FieldDev *F;
+  const void *mlp;
+  int mlp_bytes;
+  const MarchJob *jobs;
+  int n_jobs;
+  const uint32_t *ent_ray;
+  const int *ent_cnt;
+  const float2 *ent_u;
+  const float *wr, *wg, *wb;
+  const void *feat;
+  int64_t n_slots;
+  int n_entries;
+  float *acc;
+};
+
+struct WfResolveArgs {
+  const MarchJob *jobs;
+  int n_jobs;
+  const int64_t *pix_begin;  // per job, plus the total at [n_jobs]
+  const float *acc;
+  int tile_w, tile_h;
+};
+
+// Job of ray r: the last job whose first ray is <= r.
+__device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, int64_t r) {
+  int lo = 0, hi = n_jobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].ray_begin <= r) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename VT, int DIRECT>
+__global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
+  __shared__ float4 tf[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) tf[i] = a.m.tf[i];
+  __syncthreads();
+  const int n_in = a.n_cont + a.n_fresh;
+  const int needed = (n_in + WF_THREADS - 1) / WF_THREADS;
+  // XCD-aware order: XCD x (blockIdx % 8) takes a contiguous run of entries
+  const int per = (int)(gridDim.x >> 3);
+  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (b >= needed) return;
+  const int lane = lane_id();
+  const int t = b * WF_THREADS + (int)threadIdx.x;
+  bool active = t < n_in;
+  uint32_t r = 0;
+  int j = 0;
+  float T = 1.0f;
+  bool fresh = true;
+  if (active) {
+    if (t < a.n_cont) {
+      r = a.in_ray[t];
+      j = a.in_j[t];
+      T = a.in_T[t];
+      fresh = false;
+    } else {
+      r = (uint32_t)(a.fresh_begin + (t - a.n_cont));
+    }
+  }
+  MarchJob job = a.m.jobs[find_job_ray(a.m.jobs, a.m.n_jobs, (int64_t)r)];
+  int px = 0, py = 0, s = 0;
+  {
+    const int64_t rr = (int64_t)r - job.ray_begin;
+    const int64_t per_s = (int64_t)job.tiles * 64;
+    s = (int)(rr / per_s);
+    const int rem = (int)(rr - (int64_t)s * per_s);
+    const int tile = rem >> 6, ln = rem & 63;
+    px = (tile % job.tiles_x) * a.m.tile_w + ln % a.m.tile_w;
+    py = (tile / job.tiles_x) * a.m.tile_h + ln / a.m.tile_w;
+  }
+  const bool pixel_ok = active && px < job.width && py < job.height;
+
+  const f3 eye = {job.eye[0], job.eye[1], job.eye[2]};
+  f3 d = {0.f, 0.f, 1.f}, wo = {0.f, 0.f, -1.f};
+  float t0 = 0.f, span = 0.f, xi = 0.5f, u0 = 0.f, u1 = 0.f;
+  int n = 0;
+  bool live = false;
+  if (pixel_ok) {
+    float jx = 0.5f, jy = 0.5f;
+    if (job.spp > 1) {
+      Philox rng;
+      rng.init(job.seed, ((uint64_t)py * job.width + px) * (uint64_t)job.spp + (uint64_t)s,
+               STREAM_RENDER);
+      jx = rng.next();
+      jy = rng.next();
+      xi = rng.next();
+    }
+    const f3 fw = {job.fwd[0], job.fwd[1], job.fwd[2]};
+    const f3 rt = {job.right[0], job.right[1], job.right[2]};
+    const f3 up = {job.up[0], job.up[1], job.up[2]};
+    float sx = 2.0f * ((float)px + jx) / (float)job.width - 1.0f;
+    float sy = 1.0f - 2.0f * ((float)py + jy) / (float)job.height;
+    d = normalize3(fw + rt * sx + up * sy);
+    wo = d * -1.0f;
+    float t1;
+    if (clip_cube(eye, d, t0, t1)) {
+      span = t1 - t0;
+      float ns = ceilf(span / job.step);
+      n = ns > (float)job.max_steps ? job.max_steps : (int)ns;
+      dir_coords_f(wo, u0, u1);
+      live = n > j;
+    }
+  }
+
+  f3 Cs = {0.f, 0.f, 0.f};
+  int cnt = 0;
+  bool finished = !live;
+  unsigned n_steps = 0;
+  const size_t slot0 = (size_t)t * WF_SLOTS;
+  while (!finished && cnt < WF_SLOTS) {
+    f3 W = {0.f, 0.f, 0.f};
+    f3 xq = {0.f, 0.f, 0.f};
+    for (int k = 0; k < job.stride; ++k) {
+      float l = fminf(job.step, span - (float)j * job.step);
+      if (!(l > 0.0f)) {
+        finished = true;
+        break;
+      }
+      float tt = t0 + (float)j * job.step + xi * l;
+      f3 x = eye + d * tt;
+      float rho = density_at(reinterpret_cast<const VT *>(a.m.vol), a.m.vg, x);
+      float4 o = tf_lookup(tf, rho);
+      float sig = o.w * a.m.ext_scale;
+      float alpha = -expm1f(-sig * l);
+      float att = 1.0f - alpha;
+      f3 alb = {o.x, o.y, o.z};
+      f3 Ld = direct_light<VT, DIRECT>(a.m, job, tf, x, wo);
+      f3 wgt = alb * (T * alpha);
+      ++n_steps;
+      if (k == 0) xq = x;
+      Cs = Cs + mul(wgt, Ld);
+      W = W + wgt;
+      T *= att;
+      ++j;
+      if (j >= n || T < job.t_min) {
+        finished = true;
+        break;
+      }
+    }
+    if (W.x != 0.f || W.y != 0.f || W.z != 0.f) {
+      const size_t q = slot0 + cnt;
+      a.qx[q] = xq.x;
+      a.qy[q] = xq.y;
+      a.qz[q] = xq.z;
+      a.wr[q] = W.x;
+      a.wg[q] = W.y;
+      a.wb[q] = W.z;
+      ++cnt;
+    }
+  }
+  if (active) {
+    a.ent_cnt[t] = cnt;
+    a.ent_ray[t] = r;
+    a.ent_u[t] = make_float2(u0, u1);
+  }
+  if (pixel_ok) {
+    float *ac = a.acc + (size_t)r * 3;
+    if (fresh) {
+      ac[0] = Cs.x;
+      ac[1] = Cs.y;
+      ac[2] = Cs.z;
+    } else {
+      ac[0] += Cs.x;
+      ac[1] += Cs.y;
+      ac[2] += Cs.z;
+    }
+    if (a.m.counters) {
+      atomicAdd(&a.m.counters[0], (unsigned long long)n_steps);
+      atomicAdd(&a.m.counters[1], (unsigned long long)cnt);
+    }
+  }
+  // rays that filled their slots continue next round (one atomic per wave)
+  const bool cont = pixel_ok && !finished;
+  const uint64_t m = __builtin_amdgcn_ballot_w64(cont);
+  if (m) {
+    const int leader = __builtin_ctzll(m);
+    unsigned base = 0;
+    if (lane == leader) base = atomicAdd(a.out_count, (unsigned)__builtin_popcountll(m));
+    base = __shfl(base, leader);
+    if (cont) {
+      const unsigned idx = base + (unsigned)__builtin_popcountll(m & ((1ull << lane) - 1ull));
+      a.out_ray[idx] = r;
+      a.out_j[idx] = j;
+      a.out_T[idx] = T;
+    }
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void store_feat(void *feat, int64_t i, float2 v) {
+  if constexpr (P == P_F32) {
+    reinterpret_cast<float2 *>(feat)[i] = v;
+  } else if constexpr (P == P_F16) {
+    __half2 h = __floats2half2_rn(v.x, v.y);
+    reinterpret_cast<uint32_t *>(feat)[i] = *reinterpret_cast<uint32_t *>(&h);
+  } else {
+    __bf16 lo = (__bf16)v.x, hi = (__bf16)v.y;
+    uint32_t w = (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+                 ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+    reinterpret_cast<uint32_t *>(feat)[i] = w;
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
+  const int64_t s = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
+  if (s >= e.n_slots) return;
+  const int64_t t = s / WF_SLOTS;
+  const int c = (int)(s - t * WF_SLOTS);
+  if (c >= e.ent_cnt[t]) return;
+  const FieldDev &F = *e.F;
+  const f3 x = clamp01(f3{e.qx[s], e.qy[s], e.qz[s]});
+  for (int lv = e.l0; lv < e.l1; ++lv)
+    store_feat<P>(e.feat, (int64_t)lv * e.n_slots + s, encode_pos_level<P>(F, lv, x));
+}
+
+template <int P>
+__device__ __forceinline__ float2 load_feat2(const void *feat, int64_t i) {
+  if constexpr (P == P_F32) return reinterpret_cast<const float2 *>(feat)[i];
+  else return load_feat<P>(reinterpret_cast<const uint32_t *>(feat) + i, 0u);
+}
+
+template <int P>
+__global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_w[];
+  stage_weights(lds_w, a.mlp, a.mlp_bytes);
+  __syncthreads();
+  const FieldDev &F = *a.F;
+  const int lane = lane_id(), q = lane >> 4, c = lane & 15;
+  const int waves = (int)gridDim.x * (WF_THREADS / 64);
+  for (int t = (int)blockIdx.x * (WF_THREADS / 64) + (int)(threadIdx.x >> 6); t < a.n_entries;
+       t += waves) {
+    const int cnt = a.ent_cnt[t];
+    if (cnt == 0) continue;
+    const uint32_t r = a.ent_ray[t];
+    const float g = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
+    const float2 u = a.ent_u[t];
+    const int64_t s = (int64_t)t * WF_SLOTS + c;
+    const bool valid = c < cnt;
+    float pos[8], dir[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int lv = 4 * q + k;
+      float2 fp = make_float2(0.0f, 0.0f), fd = make_float2(0.0f, 0.0f);
+      if (lv < F.levels) {
+        if (valid) fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + s);
+        fd = encode_dir_level<P>(F, lv, (double)u.x, (double)u.y);
+      }
+      pos[2 * k] = fp.x;
+      pos[2 * k + 1] = fp.y;
+      dir[2 * k] = fd.x;
+      dir[2 * k + 1] = fd.y;
+    }
+    const float gin = (q == 0) ? g : 0.0f;
+    f32x4 out;
+    if constexpr (P == P_F32) {
+      out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w), F.hidden, pos, dir, gin);
+    } else {
+      typedef Mma<P> M;
+      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+      out = mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w), F.hidden,
+                             M::pack(pos), M::pack(dir), M::pack(gz));
+    }
+    // lanes 0..15 hold the decoded output of query c; weight by W and sum in a fixed order
+    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+    if (q == 0 && valid) {
+      v0 = a.wr[s] * decode_lp(out[0], F.psi, F.kappa);
+      v1 = a.wg[s] * decode_lp(out[1], F.psi, F.kappa);
+      v2 = a.wb[s] * decode_lp(out[2], F.psi, F.kappa);
+    }
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) {
+      v0 += __shfl_xor(v0, o);
+      v1 += __shfl_xor(v1, o);
+      v2 += __shfl_xor(v2, o);
+    }
+    if (lane == 0) {
+      float *ac = a.acc + (size_t)r * 3;
+      ac[0] += v0;
+      ac[1] += v1;
+      ac[2] += v2;
+    }
+  }
+}
+
+__global__ void wf_resolve_kernel(WfResolveArgs a) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.pix_begin[a.n_jobs]) return;
+  int lo = 0, hi = a.n_jobs - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (a.pix_begin[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  const MarchJob &job = a.jobs[lo];
+  const int pi = (int)(p - a.pix_begin[lo]);
+  const int x = pi % job.width, y = pi / job.width;
+  const int tile = (y / a.tile_h) * job.tiles_x + x / a.tile_w;
+  const int ln = (y % a.tile_h) * a.tile_w + x % a.tile_w;
+  const int64_t per_s = (int64_t)job.tiles * 64;
+  f3 C = {0.f, 0.f, 0.f};
+  for (int s = 0; s < job.spp; ++s) {
+    const float *ac = a.acc + (size_t)(job.ray_begin + s * per_s + tile * 64 + ln) * 3;
+    C = C + f3{ac[0], ac[1], ac[2]};
+  }
+  float *o = job.out + (size_t)pi * 3;
+  o[0] = C.x * job.inv_spp;
+  o[1] = C.y * job.inv_spp;
+  o[2] = C.z * job.inv_spp;
+}
+
+// ------------------------------------------------------------------ host side
+template <typename T>
+static hipError_t alloc_n(T *&p, size_t n) {
+  return hipMalloc((void **)&p, sizeof(T) * n);
+}
+
+static void free_entries(WfState &w) {
+  for (int i = 0; i < 2; ++i) {
+    (void)hipFree(w.list_ray[i]);
+    (void)hipFree(w.list_j[i]);
+    (void)hipFree(w.list_T[i]);
+    w.list_ray[i] = nullptr;
+    w.list_j[i] = nullptr;
+    w.list_T[i] = nullptr;
+  }
+  (void)hipFree(w.ent_ray);
+  (void)hipFree(w.ent_cnt);
+  (void)hipFree(w.ent_u);
+  w.ent_ray = nullptr;
+  w.ent_cnt = nullptr;
+  w.ent_u = nullptr;
+  for (int i = 0; i < 6; ++i) {
+    (void)hipFree(w.slot[i]);
+    w.slot[i] = nullptr;
+  }
+  (void)hipFree(w.feat);
+  w.feat = nullptr;
+  w.ent_cap = 0;
+  w.feat_elem = 0;
+}
+
+// Buffers for `entries` rays per round, `rays` ray samples per frame and feature elements of
+// `feat_bytes` bytes; kept between frames and grown on demand.
+static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes) {
+  hipError_t e = hipSuccess;
+  if (entries > w.ent_cap || feat_bytes > w.feat_elem) {
+    free_entries(w);
+    for (int i = 0; i < 2; ++i) {
+      if ((e = alloc_n(w.list_ray[i], entries))) return e;
+      if ((e = alloc_n(w.list_j[i], entries))) return e;
+      if ((e = alloc_n(w.list_T[i], entries))) return e;
+    }
+    if ((e = alloc_n(w.ent_ray, entries))) return e;
+    if ((e = alloc_n(w.ent_cnt, entries))) return e;
+    if ((e = alloc_n(w.ent_u, entries))) return e;
+    for (int i = 0; i < 6; ++i)
+      if ((e = alloc_n(w.slot[i], entries * WF_SLOTS))) return e;
+    unsigned char *fp = nullptr;
+    if ((e = alloc_n(fp, entries * WF_SLOTS * PFN_MAX_LEVELS * feat_bytes))) return e;
+    w.feat = fp;
+    w.ent_cap = entries;
+    w.feat_elem = feat_bytes;
+  }
+  if (rays * 3 > w.acc_cap) {
+    (void)hipFree(w.acc);
+    w.acc = nullptr;
+    w.acc_cap = 0;
+    if ((e = alloc_n(w.acc, rays * 3))) return e;
+    w.acc_cap = rays * 3;
+  }
+  if (!w.count) {
+    if ((e = hipMalloc((void **)&w.count, 16))) return e;
+    if ((e = hipHostMalloc((void **)&w.host_count, 16, hipHostMallocDefault))) return e;
+  }
+  return hipSuccess;
+}
+
+void wf_release(WfState &w) {
+  free_entries(w);
+  (void)hipFree(w.acc);
+  (void)hipFree(w.count);
+  if (w.host_count) (void)hipHostFree(w.host_count);
+  (void)hipFree(w.pix_begin);
+  w = WfState{};
+}
+
+template <typename VT, int DIRECT>
+static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL((wf_march_kernel<VT, DIRECT>), dim3(blocks), dim3(WF_THREADS), 0, st, a);
+}
+
+template <int P>
+static void launch_k23(pfn_context *ctx, const WfEncArgs &e,
+                       const std::vector<std::pair<int, int>> &groups, const WfFieldArgs &f,
+                       int field_blocks) {
+  const int eb = (int)((e.n_slots + WF_THREADS - 1) / WF_THREADS);
+  for (auto &g : groups) {
+    WfEncArgs ee = e;
+    ee.l0 = g.first;
+    ee.l1 = g.second;
+    const int ts = timing_begin(ctx);
+    hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, ctx->stream, ee);
+    timing_end(ctx, ts, TK_WF_ENCODE);
+  }
+  const int ts = timing_begin(ctx);
+  hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
+                     (size_t)f.mlp_bytes, ctx->stream, f);
+  timing_end(ctx, ts, TK_WF_FIELD);
+}
+
+pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
+                         int direct, int prec, int slot, const FieldDev &fd_host) {
+  WfState &w = ctx->wf;
+  // ray layout and pixel offsets of the jobs
+  int64_t rays = 0, pixels = 0;
+  std::vector<int64_t> pix_begin(mj.size() + 1);
+  for (size_t i = 0; i < mj.size(); ++i) {
+    mj[i].ray_begin = rays;
+    rays += (int64_t)mj[i].spp * mj[i].tiles * 64;
+    pix_begin[i] = pixels;
+    pixels += (int64_t)mj[i].width * mj[i].height;
+  }
+  pix_begin[mj.size()] = pixels;
+  if (rays >= (int64_t)1 << 31)
+    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "wavefront render: more than 2^31 ray samples");
+  const size_t entries = (size_t)std::min<int64_t>(rays, WF_MAX_ENTRIES);
+  const size_t fbytes = prec == P_F32 ? 8 : 4;
+  PFN_HIP(ctx, wf_reserve(w, entries, (size_t)rays, fbytes));
+  if (w.pix_cap < mj.size() + 1) {
+    (void)hipFree(w.pix_begin);
+    w.pix_begin = nullptr;
+    w.pix_cap = 0;
+    PFN_HIP(ctx, hipMalloc((void **)&w.pix_begin, sizeof(int64_t) * (mj.size() + 1)));
+    w.pix_cap = mj.size() + 1;
+  }
+  PFN_HIP(ctx, hipMemcpyAsync(ctx->jobs_dev, mj.data(), sizeof(MarchJob) * mj.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+  PFN_HIP(ctx, hipMemcpyAsync(w.pix_begin, pix_begin.data(), sizeof(int64_t) * pix_begin.size(),
+                              hipMemcpyHostToDevice, ctx->stream));
+  PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+  // level groups of the position encoding: the coarse levels together, each fine hashed
+  // level alone
+  std::vector<std::pair<int, int>> groups;
+  {
+    int l = 0;
+    const int L = fd_host.levels;
+    while (l < L) {
+      const bool fine = !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
+      if (fine) {
+        groups.push_back({l, l + 1});
+        ++l;
+      } else {
+        int e = l;
+        while (e < L && !(!((fd_host.pos.dense_mask >> e) & 1u) && fd_host.pos.res[e] >= WF_FINE_RES))
+          ++e;
+        groups.push_back({l, e});
+        l = e;
+      }
+    }
+  }
+
+  WfArgs a{};
+  a.m = m;
+  a.out_count = w.count;
+  a.ent_ray = w.ent_ray;
+  a.ent_cnt = w.ent_cnt;
+  a.ent_u = w.ent_u;
+  a.qx = w.slot[0];
+  a.qy = w.slot[1];
+  a.qz = w.slot[2];
+  a.wr = w.slot[3];
+  a.wg = w.slot[4];
+  a.wb = w.slot[5];
+  a.acc = w.acc;
+
+  WfEncArgs e{};
+  e.F = m.fields + slot;
+  e.ent_cnt = w.ent_cnt;
+  e.qx = w.slot[0];
+  e.qy = w.slot[1];
+  e.qz = w.slot[2];
+  e.feat = w.feat;
+
+  WfFieldArgs f{};
+  f.F = m.fields + slot;
+  f.mlp = ctx->fields[slot].mlp_packed[prec];
+  f.mlp_bytes = m.mlp_bytes;
+  f.jobs = m.jobs;
+  f.n_jobs = m.n_jobs;
+  f.ent_ray = w.ent_ray;
+  f.ent_cnt = w.ent_cnt;
+  f.ent_u = w.ent_u;
+  f.wr = w.slot[3];
+  f.wg = w.slot[4];
+  f.wb = w.slot[5];
+  f.feat = w.feat;
+  f.acc = w.acc;
+
+  const int tslot = timing_begin(ctx);
+  int64_t fresh_next = 0;
+  int n_cont = 0, cur = 0;
+  while (fresh_next < rays || n_cont > 0) {
+    const int n_fresh = (int)std::min<int64_t>((int64_t)entries - n_cont, rays - fresh_next);
+    const int n_in = n_cont + n_fresh;
+    a.in_ray = w.list_ray[cur];
+    a.in_j = w.list_j[cur];
+    a.in_T = w.list_T[cur];
+    a.out_ray = w.list_ray[cur ^ 1];
+    a.out_j = w.list_j[cur ^ 1];
+    a.out_T = w.list_T[cur ^ 1];
+    a.n_cont = n_cont;
+    a.n_fresh = n_fresh;
+    a.fresh_begin = fresh_next;
+    PFN_HIP(ctx, hipMemsetAsync(w.count, 0, 4, ctx->stream));
+    const int needed = (n_in + WF_THREADS - 1) / WF_THREADS;
+    const int k1_blocks = ((needed + 7) / 8) * 8;
+    const int ts1 = timing_begin(ctx);
+    if (ctx->vol_dtype == PFN_F16) {
+      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<__half, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, ctx->stream);
+      else launch_k1<__half, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, ctx->stream);
+    } else {
+      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<float, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, ctx->stream);
+      else launch_k1<float, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, ctx->stream);
+    }
+    timing_end(ctx, ts1, TK_WF_MARCH);
+    PFN_HIP(ctx, hipGetLastError());
+    e.n_slots = (int64_t)n_in * WF_SLOTS;
+    f.n_slots = e.n_slots;
+    f.n_entries = n_in;
+    const int fb = std::max(1, std::min((n_in + 3) / 4, 256 * 8));
+    if (prec == P_F32) launch_k23<P_F32>(ctx, e, groups, f, fb);
+    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, e, groups, f, fb);
+    else launch_k23<P_F16>(ctx, e, groups, f, fb);
+    PFN_HIP(ctx, hipGetLastError());
+    PFN_HIP(ctx, hipMemcpyAsync(w.host_count, w.count, 4, hipMemcpyDeviceToHost, ctx->stream));
+    PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    fresh_next += n_fresh;
+    n_cont = (int)w.host_count[0];
+    cur ^= 1;
+  }
+  WfResolveArgs ra{};
+  ra.jobs = m.jobs;
+  ra.n_jobs = m.n_jobs;
+  ra.pix_begin = w.pix_begin;
+  ra.acc = w.acc;
+  ra.tile_w = m.tile_w;
+  ra.tile_h = m.tile_h;
+  const int tsr = timing_begin(ctx);
+  hipLaunchKernelGGL(wf_resolve_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0,
+                     ctx->stream, ra);
+  timing_end(ctx, tsr, TK_WF_RESOLVE);
+  PFN_HIP(ctx, hipGetLastError());
+  timing_end(ctx, tslot, TK_MARCH);
+  return PFN_OK;
+}

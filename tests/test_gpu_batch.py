@@ -1,4 +1,4 @@
-"""Batched ray-march launch: many jobs of uneven sizes, cameras, lights, g and field slots in one
+"""Batched ray-march launch of the fused kernel: many jobs of uneven sizes, cameras, lights, g and field slots in one
 launch (plain or persistent, immediate or replayed from a captured HIP graph), bit-identical to
 rendering each job alone, and checked against the FP64 oracle."""
 import numpy as np
@@ -19,6 +19,7 @@ def bctx(orc):
     w, vol, tf, _ = scene_arrays("c0")
     lights = sg.lights_array(sg.make_lights(4, 55))
     ctx = gpu_context(vol, tf, lights)
+    ctx.set_render_strategy("fused")  # the persistent and graph launches are fused kernels
     ctx.build_light_volume(0.5)
     for slot in (0, 1):
         ctx.field_select(slot)

@@ -107,13 +107,15 @@ def test_field_query_empty_and_tiny(orc, fctx):
     assert np.abs(lp.cpu().numpy() - ref).max() <= 1e-5
 
 
-def test_render_with_field_parity(orc):
+@pytest.mark.parametrize("strategy", ["fused", "wavefront"])
+def test_render_with_field_parity(orc, strategy):
     import torch
     from paper_2304_07338_amd import scenegen as sg
     from paper_2304_07338_amd.pfn import FieldConfig, RenderConfig, INDIRECT_FIELD
-    say("render with the field (f32), stride 4, 24x20")
+    say(f"render with the field, stride 4, 24x20 ({strategy})")
     w, vol, tf, lights = scene_arrays("c0")
     ctx = gpu_context(vol, tf, lights)
+    ctx.set_render_strategy(strategy)
     cfg = FieldConfig(**C1_FIELD)
     desc = oracle_desc(orc, cfg)
     ctx.field_select(0)
