@@ -209,6 +209,10 @@ FieldDev make_field_dev(const FieldSlot &f, int prec) {
     F.dir_table = f.lp_table[prec] + f.pos_entries;
   }
   F.hash_mask = (uint32_t)((1ull << f.desc.log2_table) - 1);
+  // wide loads of entry pairs need each table to start at a multiple of two entries
+  const size_t pair_bytes = prec == P_F32 ? 16 : 8;
+  F.pair_ok = (((uintptr_t)F.pos_table % pair_bytes) == 0 ? 1u : 0u) |
+              (((uintptr_t)F.dir_table % pair_bytes) == 0 ? 2u : 0u);
   F.levels = f.desc.levels;
   F.hidden = f.desc.hidden_layers;
   F.psi = f.desc.psi;

@@ -51,12 +51,16 @@ struct WfState {
   uint32_t *list_ray[2] = {nullptr, nullptr};  // continuing rays, ping-pong between rounds
   int *list_j[2] = {nullptr, nullptr};
   float *list_T[2] = {nullptr, nullptr};
+  float *list_cd[2] = {nullptr, nullptr};      // carried direct and indirect RGB sums
+  float *list_ci[2] = {nullptr, nullptr};
   uint32_t *ent_ray = nullptr;
   int *ent_cnt = nullptr;
+  int *ent_next = nullptr;
   float2 *ent_u = nullptr;
   float *slot[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // x y z, W rgb
-  void *feat = nullptr;
-  float *acc = nullptr;
+  void *feat = nullptr;   // position features [level][slot]
+  void *dfeat = nullptr;  // direction features [level][entry]
+  float *acc_d = nullptr, *acc_i = nullptr;  // final sums per ray sample
   unsigned *count = nullptr;       // device counter of continuing rays
   unsigned *host_count = nullptr;  // pinned copy
   int64_t *pix_begin = nullptr;

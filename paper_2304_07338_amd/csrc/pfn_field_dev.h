@@ -35,6 +35,7 @@ struct FieldDev {
   const void *pos_table;  // f32: float2 per entry; f16/bf16: 2 packed 16-bit features per entry
   const void *dir_table;
   uint32_t hash_mask;     // 2^log2_table - 1
+  uint32_t pair_ok;       // bit 0 / 1: the position / direction table starts on a pair of entries
   int levels;
   int hidden;             // hidden layers
   float psi, kappa;
@@ -63,17 +64,47 @@ __device__ __forceinline__ void level_cell(float x, int N, int &c, float &f) {
 }
 
 template <int P>
+__device__ __forceinline__ float2 unpack_feat(uint32_t v) {
+  if constexpr (P == P_F16) {
+    __half2 h = *reinterpret_cast<__half2 *>(&v);
+    return __half22float2(h);
+  } else {
+    return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xFFFF0000u));
+  }
+}
+
+template <int P>
 __device__ __forceinline__ float2 load_feat(const void *table, uint32_t e) {
   if constexpr (P == P_F32) {
     return reinterpret_cast<const float2 *>(table)[e];
   } else {
-    uint32_t v = reinterpret_cast<const uint32_t *>(table)[e];
-    if constexpr (P == P_F16) {
-      __half2 h = *reinterpret_cast<__half2 *>(&v);
-      return __half22float2(h);
+    return unpack_feat<P>(reinterpret_cast<const uint32_t *>(table)[e]);
+  }
+}
+
+// Features of the entries e0 and e1 of the two x-neighbours of a cell edge.  When they form one
+// aligned pair of entries, one wide load fetches both: on a hashed level that is every even x
+// (the first hash prime is 1, so the two indices differ in bit 0 only), on a dense level every
+// even e0.  Halving the loads matters on the fine hashed levels, where every corner pair is a
+// separate cache line.
+template <int P>
+__device__ __forceinline__ void load_feat_pair(const void *table, bool pair_ok, uint32_t e0,
+                                               uint32_t e1, float2 &v0, float2 &v1) {
+  if (pair_ok && (e0 ^ e1) == 1u) {
+    const bool swap = (e0 & 1u) != 0u;
+    if constexpr (P == P_F32) {
+      const float4 pr = reinterpret_cast<const float4 *>(table)[e0 >> 1];
+      const float2 lo = make_float2(pr.x, pr.y), hi = make_float2(pr.z, pr.w);
+      v0 = swap ? hi : lo;
+      v1 = swap ? lo : hi;
     } else {
-      return make_float2(__uint_as_float(v << 16), __uint_as_float(v & 0xFFFF0000u));
+      const uint2 pr = reinterpret_cast<const uint2 *>(table)[e0 >> 1];
+      v0 = unpack_feat<P>(swap ? pr.y : pr.x);
+      v1 = unpack_feat<P>(swap ? pr.x : pr.y);
     }
+  } else {
+    v0 = load_feat<P>(table, e0);
+    v1 = load_feat<P>(table, e1);
   }
 }
 
@@ -90,16 +121,22 @@ __device__ __forceinline__ float2 encode_pos_level(const FieldDev &F, int lv, f3
   level_cell(x.z, N, cz, fz);
   float2 acc = make_float2(0.0f, 0.0f);
   uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+  const bool pair_ok = (F.pair_ok & 1u) != 0u;
+  const float gx = 1.0f - fx;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1)),
+  for (int k = 0; k < 8; k += 2) {  // corners k (x0) and k+1 (x1) share y and z
+    uint32_t vx = (uint32_t)cx, vy = (uint32_t)(cy + ((k >> 1) & 1)),
              vz = (uint32_t)(cz + ((k >> 2) & 1));
-    uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
-    float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy) *
-              (((k >> 2) & 1) ? fz : 1.0f - fz);
-    float2 v = load_feat<P>(F.pos_table, off + idx);
-    acc.x = fmaf(w, v.x, acc.x);
-    acc.y = fmaf(w, v.y, acc.y);
+    uint32_t i0 = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+    uint32_t i1 = dense ? (i0 + 1u) : (hash3(vx + 1u, vy, vz) & F.hash_mask);
+    float wy = ((k >> 1) & 1) ? fy : 1.0f - fy, wz = ((k >> 2) & 1) ? fz : 1.0f - fz;
+    float2 v0, v1;
+    load_feat_pair<P>(F.pos_table, pair_ok, off + i0, off + i1, v0, v1);
+    float w0 = gx * wy * wz, w1 = fx * wy * wz;
+    acc.x = fmaf(w0, v0.x, acc.x);
+    acc.y = fmaf(w0, v0.y, acc.y);
+    acc.x = fmaf(w1, v1.x, acc.x);
+    acc.y = fmaf(w1, v1.y, acc.y);
   }
   return acc;
 }
@@ -124,14 +161,20 @@ __device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, do
   level_cell_d(u1, N, cy, fy);
   float2 acc = make_float2(0.0f, 0.0f);
   uint32_t s1 = (uint32_t)(N + 1);
+  const bool pair_ok = (F.pair_ok & 2u) != 0u;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1));
-    uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
-    float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy);
-    float2 v = load_feat<P>(F.dir_table, off + idx);
-    acc.x = fmaf(w, v.x, acc.x);
-    acc.y = fmaf(w, v.y, acc.y);
+  for (int k = 0; k < 4; k += 2) {  // corners k (x0) and k+1 (x1) share y
+    uint32_t vx = (uint32_t)cx, vy = (uint32_t)(cy + ((k >> 1) & 1));
+    uint32_t i0 = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+    uint32_t i1 = dense ? (i0 + 1u) : (hash2(vx + 1u, vy) & F.hash_mask);
+    float wy = ((k >> 1) & 1) ? fy : 1.0f - fy;
+    float2 v0, v1;
+    load_feat_pair<P>(F.dir_table, pair_ok, off + i0, off + i1, v0, v1);
+    float w0 = (1.0f - fx) * wy, w1 = fx * wy;
+    acc.x = fmaf(w0, v0.x, acc.x);
+    acc.y = fmaf(w0, v0.y, acc.y);
+    acc.x = fmaf(w1, v1.x, acc.x);
+    acc.y = fmaf(w1, v1.y, acc.y);
   }
   return acc;
 }

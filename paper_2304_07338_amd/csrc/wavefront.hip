@@ -1,6 +1,6 @@
 // Wavefront form of the photon-field ray marcher (Section 3.6 with Eq. (3): the field supplies
 // L_i at the samples of a ray marcher).  The fused kernel keeps a ray and its field queries in
-// one wave; here the frame runs in rounds of four kernels so that each piece runs at its own
+// one wave; here a frame runs in rounds of small kernels so that each piece runs at its own
 // best occupancy and the fine hash levels of the position encoding stay resident in L2:
 //
 //   1. wf_march_kernel: one lane per ray (a pixel sample).  The lane marches groups of `stride`
@@ -12,14 +12,16 @@
 //      the 16-bit (or FP32) features the matrix cores consume.  One launch covers the coarse
 //      levels; each fine hashed level (cells smaller than the spacing of neighbouring queries)
 //      gets a launch of its own so that its 2 MB table is the only grid table the L2 holds.
-//   3. wf_field_kernel: one wave per ray of the round: the direction encoding (shared by all
-//      queries of the ray), the MLP of its 16 queries on the matrix cores, the Eq. (7) decode,
-//      and the sum of W * L_i over the queries in a fixed order, added to the ray's sum.
+//      wf_dir_kernel encodes the view direction once per ray of the round.
+//   3. wf_field_kernel: one wave per ray of the round: the MLP of its 16 queries on the matrix
+//      cores, the Eq. (7) decode, and the sum of W * L_i over the queries in a fixed order.
 //   4. after the last round, wf_resolve_kernel averages each pixel's samples.
 //
-// Every ray's arithmetic is the fused kernel's; only the order in which the W * L_i terms are
-// added to the pixel differs.  Results do not depend on the lane or list position a ray gets,
-// so a frame is deterministic and a batch renders exactly as its jobs rendered alone.
+// A ray carries its direct sum and its indirect sum in the list from round to round and
+// stores them once, when it ends; no kernel reads and rewrites a pixel.  Every ray's arithmetic
+// is the fused kernel's; only the order in which the FP32 terms are added differs.  Results do
+// not depend on the lane or list position a ray gets, so a frame is deterministic and a batch
+// renders exactly as its jobs rendered alone.
 #include "march.h"
 #include "march_dev.h"
 #include "pfn_ctx.h"
@@ -29,25 +31,30 @@
 #define WF_MAX_ENTRIES (1 << 21)     // rays per round
 #define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
 
+// Rays continued from the previous round: ray id, next step, transmittance and the direct and
+// indirect sums so far (RGB, entry-major).
+struct WfList {
+  uint32_t *ray;
+  int *j;
+  float *T;
+  float *cd;
+  float *ci;
+};
+
 struct WfArgs {
   MarchArgs m;
-  // continuing rays of the previous round (entries [0, n_cont)) followed by fresh rays
-  const uint32_t *in_ray;
-  const int *in_j;
-  const float *in_T;
+  WfList in, out;     // in: entries [0, n_cont); out: appended through out_count
   int n_cont, n_fresh;
   int64_t fresh_begin;
-  uint32_t *out_ray;
-  int *out_j;
-  float *out_T;
   unsigned *out_count;
   // per entry of this round
   uint32_t *ent_ray;
   int *ent_cnt;
+  int *ent_next;      // index of the entry's ray in the out list, or -1 when the ray ended
   float2 *ent_u;
   // per query slot (entry * WF_SLOTS + k)
   float *qx, *qy, *qz, *wr, *wg, *wb;
-  float *acc;  // per ray: RGB sum of the sample
+  float *acc_d, *acc_i;  // per ray sample: final direct and indirect RGB sums
 };
 
 struct WfEncArgs {
@@ -59,6 +66,14 @@ struct WfEncArgs {
   int l0, l1;
 };
 
+struct WfDirArgs {
+  const FieldDev *F;
+  const int *ent_cnt;
+  const float2 *ent_u;
+  void *dfeat;          // [level][entry]
+  int n_entries;
+};
+
 struct WfFieldArgs {
   const FieldDev *F;
   const void *mlp;
@@ -67,19 +82,21 @@ struct WfFieldArgs {
   int n_jobs;
   const uint32_t *ent_ray;
   const int *ent_cnt;
-  const float2 *ent_u;
+  const int *ent_next;
   const float *wr, *wg, *wb;
-  const void *feat;
+  const void *feat, *dfeat;
+  const float *in_ci;   // carried indirect sums of the continued entries [0, n_cont)
+  float *out_ci;
+  float *acc_i;
   int64_t n_slots;
-  int n_entries;
-  float *acc;
+  int n_entries, n_cont;
 };
 
 struct WfResolveArgs {
   const MarchJob *jobs;
   int n_jobs;
   const int64_t *pix_begin;  // per job, plus the total at [n_jobs]
-  const float *acc;
+  const float *acc_d, *acc_i;
   int tile_w, tile_h;
 };
 
@@ -94,35 +111,12 @@ __device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, in
   return lo;
 }
 
+// One ray of the round (see wf_march_kernel); `job` is uniform across the calling lanes.
 template <typename VT, int DIRECT>
-__global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
-  __shared__ float4 tf[256];
-  for (int i = threadIdx.x; i < 256; i += blockDim.x) tf[i] = a.m.tf[i];
-  __syncthreads();
-  const int n_in = a.n_cont + a.n_fresh;
-  const int needed = (n_in + WF_THREADS - 1) / WF_THREADS;
-  // XCD-aware order: XCD x (blockIdx % 8) takes a contiguous run of entries
-  const int per = (int)(gridDim.x >> 3);
-  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (b >= needed) return;
+__device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, const MarchJob &job,
+                                            int t, bool active, bool fresh, uint32_t r, int j,
+                                            float T, f3 Cd) {
   const int lane = lane_id();
-  const int t = b * WF_THREADS + (int)threadIdx.x;
-  bool active = t < n_in;
-  uint32_t r = 0;
-  int j = 0;
-  float T = 1.0f;
-  bool fresh = true;
-  if (active) {
-    if (t < a.n_cont) {
-      r = a.in_ray[t];
-      j = a.in_j[t];
-      T = a.in_T[t];
-      fresh = false;
-    } else {
-      r = (uint32_t)(a.fresh_begin + (t - a.n_cont));
-    }
-  }
-  MarchJob job = a.m.jobs[find_job_ray(a.m.jobs, a.m.n_jobs, (int64_t)r)];
   int px = 0, py = 0, s = 0;
   {
     const int64_t rr = (int64_t)r - job.ray_begin;
@@ -167,7 +161,6 @@ __global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
     }
   }
 
-  f3 Cs = {0.f, 0.f, 0.f};
   int cnt = 0;
   bool finished = !live;
   unsigned n_steps = 0;
@@ -193,7 +186,7 @@ __global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
       f3 wgt = alb * (T * alpha);
       ++n_steps;
       if (k == 0) xq = x;
-      Cs = Cs + mul(wgt, Ld);
+      Cd = Cd + mul(wgt, Ld);
       W = W + wgt;
       T *= att;
       ++j;
@@ -213,40 +206,87 @@ __global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
       ++cnt;
     }
   }
-  if (active) {
-    a.ent_cnt[t] = cnt;
-    a.ent_ray[t] = r;
-    a.ent_u[t] = make_float2(u0, u1);
-  }
-  if (pixel_ok) {
-    float *ac = a.acc + (size_t)r * 3;
-    if (fresh) {
-      ac[0] = Cs.x;
-      ac[1] = Cs.y;
-      ac[2] = Cs.z;
-    } else {
-      ac[0] += Cs.x;
-      ac[1] += Cs.y;
-      ac[2] += Cs.z;
-    }
-    if (a.m.counters) {
-      atomicAdd(&a.m.counters[0], (unsigned long long)n_steps);
-      atomicAdd(&a.m.counters[1], (unsigned long long)cnt);
-    }
-  }
   // rays that filled their slots continue next round (one atomic per wave)
   const bool cont = pixel_ok && !finished;
   const uint64_t m = __builtin_amdgcn_ballot_w64(cont);
+  int next = -1;
   if (m) {
     const int leader = __builtin_ctzll(m);
     unsigned base = 0;
     if (lane == leader) base = atomicAdd(a.out_count, (unsigned)__builtin_popcountll(m));
     base = __shfl(base, leader);
     if (cont) {
-      const unsigned idx = base + (unsigned)__builtin_popcountll(m & ((1ull << lane) - 1ull));
-      a.out_ray[idx] = r;
-      a.out_j[idx] = j;
-      a.out_T[idx] = T;
+      next = (int)(base + (unsigned)__builtin_popcountll(m & ((1ull << lane) - 1ull)));
+      a.out.ray[next] = r;
+      a.out.j[next] = j;
+      a.out.T[next] = T;
+      a.out.cd[3 * (size_t)next] = Cd.x;
+      a.out.cd[3 * (size_t)next + 1] = Cd.y;
+      a.out.cd[3 * (size_t)next + 2] = Cd.z;
+    }
+  }
+  if (active) {
+    a.ent_cnt[t] = pixel_ok ? cnt : 0;
+    a.ent_ray[t] = r;
+    a.ent_next[t] = next;
+    a.ent_u[t] = make_float2(u0, u1);
+  }
+  if (pixel_ok && !cont) {
+    float *ad = a.acc_d + (size_t)r * 3;
+    ad[0] = Cd.x;
+    ad[1] = Cd.y;
+    ad[2] = Cd.z;
+    if (cnt == 0) {  // no field tile this round: the indirect sum is final as carried
+      float *ai = a.acc_i + (size_t)r * 3;
+      f3 ci = {0.f, 0.f, 0.f};
+      if (!fresh) ci = {a.in.ci[3 * (size_t)t], a.in.ci[3 * (size_t)t + 1], a.in.ci[3 * (size_t)t + 2]};
+      ai[0] = ci.x;
+      ai[1] = ci.y;
+      ai[2] = ci.z;
+    }
+  }
+  if (pixel_ok && a.m.counters) {
+    atomicAdd(&a.m.counters[0], (unsigned long long)n_steps);
+    atomicAdd(&a.m.counters[1], (unsigned long long)cnt);
+  }
+}
+
+template <typename VT, int DIRECT>
+__global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
+  __shared__ float4 tf[256];
+  for (int i = threadIdx.x; i < 256; i += blockDim.x) tf[i] = a.m.tf[i];
+  __syncthreads();
+  const int n_in = a.n_cont + a.n_fresh;
+  const int needed = (n_in + WF_THREADS - 1) / WF_THREADS;
+  // XCD-aware order: XCD x (blockIdx % 8) takes a contiguous run of entries
+  const int per = (int)(gridDim.x >> 3);
+  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (b >= needed) return;
+  const int t = b * WF_THREADS + (int)threadIdx.x;
+  const bool active = t < n_in;
+  const bool fresh = t >= a.n_cont;
+  uint32_t r = 0;
+  int j = 0;
+  float T = 1.0f;
+  f3 Cd = {0.f, 0.f, 0.f};
+  if (active) {
+    if (!fresh) {
+      r = a.in.ray[t];
+      j = a.in.j[t];
+      T = a.in.T[t];
+      Cd = {a.in.cd[3 * (size_t)t], a.in.cd[3 * (size_t)t + 1], a.in.cd[3 * (size_t)t + 2]};
+    } else {
+      r = (uint32_t)(a.fresh_begin + (t - a.n_cont));
+    }
+  }
+  // waterfall over the jobs present in the wave, so that each pass reads its job descriptor
+  // into scalar registers
+  const int ji = find_job_ray(a.m.jobs, a.m.n_jobs, (int64_t)r);
+  for (bool pending = true; pending;) {
+    const int jc = __builtin_amdgcn_readfirstlane(ji);
+    if (ji == jc) {
+      march_entry<VT, DIRECT>(a, tf, a.m.jobs[jc], t, active, fresh, r, j, T, Cd);
+      pending = false;
     }
   }
 }
@@ -267,6 +307,12 @@ __device__ __forceinline__ void store_feat(void *feat, int64_t i, float2 v) {
 }
 
 template <int P>
+__device__ __forceinline__ float2 load_feat2(const void *feat, int64_t i) {
+  if constexpr (P == P_F32) return reinterpret_cast<const float2 *>(feat)[i];
+  else return load_feat<P>(reinterpret_cast<const uint32_t *>(feat) + i, 0u);
+}
+
+template <int P>
 __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   const int64_t s = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
   if (s >= e.n_slots) return;
@@ -280,9 +326,93 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
 }
 
 template <int P>
-__device__ __forceinline__ float2 load_feat2(const void *feat, int64_t i) {
-  if constexpr (P == P_F32) return reinterpret_cast<const float2 *>(feat)[i];
-  else return load_feat<P>(reinterpret_cast<const uint32_t *>(feat) + i, 0u);
+__global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
+  const int t = (int)(blockIdx.x * WF_THREADS + threadIdx.x);
+  if (t >= e.n_entries) return;
+  if (e.ent_cnt[t] == 0) return;
+  const FieldDev &F = *e.F;
+  const float2 u = e.ent_u[t];
+  for (int lv = 0; lv < F.levels; ++lv)
+    store_feat<P>(e.dfeat, (int64_t)lv * e.n_entries + t,
+                  encode_dir_level<P>(F, lv, (double)u.x, (double)u.y));
+}
+
+// Operands of one ray's tile in the field kernel: lane group q, column c.
+struct FieldTileIn {
+  int cnt, next;
+  uint32_t r;
+  f3 ci;
+  float pos[8], dir[8];
+  float w_r, w_g, w_b;
+};
+
+// Loads that depend on the entry index alone, so that all of them are in flight together.
+template <int P>
+__device__ __forceinline__ void load_tile(const WfFieldArgs &a, const FieldDev &F, int t, int q,
+                                          int c, FieldTileIn &e) {
+  e.cnt = 0;
+  e.next = -1;
+  e.r = 0;
+  e.ci = {0.f, 0.f, 0.f};
+  e.w_r = e.w_g = e.w_b = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) e.pos[k] = e.dir[k] = 0.0f;
+  if (t >= a.n_entries) return;
+  e.cnt = a.ent_cnt[t];
+  e.next = a.ent_next[t];
+  e.r = a.ent_ray[t];
+  const int64_t s = (int64_t)t * WF_SLOTS + c;
+  if (t < a.n_cont)
+    e.ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int lv = 4 * q + k;
+    float2 fp = make_float2(0.0f, 0.0f), fd = make_float2(0.0f, 0.0f);
+    if (lv < F.levels) {
+      fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + s);
+      fd = load_feat2<P>(a.dfeat, (int64_t)lv * a.n_entries + t);
+    }
+    e.pos[2 * k] = fp.x;
+    e.pos[2 * k + 1] = fp.y;
+    e.dir[2 * k] = fd.x;
+    e.dir[2 * k + 1] = fd.y;
+  }
+  if (q == 0) {
+    e.w_r = a.wr[s];
+    e.w_g = a.wg[s];
+    e.w_b = a.wb[s];
+  }
+  // columns past the ray's count, and rays without queries, hold stale buffer contents
+  const bool valid = c < e.cnt;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    e.pos[k] = valid ? e.pos[k] : 0.0f;
+    e.dir[k] = e.cnt > 0 ? e.dir[k] : 0.0f;
+  }
+}
+
+// Decode, weight by W, sum over the tile's columns in a fixed order, and store the ray's sum.
+__device__ __forceinline__ void finish_tile(const WfFieldArgs &a, const FieldDev &F,
+                                            const FieldTileIn &e, f32x4 out, int lane, int q,
+                                            int c) {
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  if (q == 0 && c < e.cnt) {
+    v0 = e.w_r * decode_lp(out[0], F.psi, F.kappa);
+    v1 = e.w_g * decode_lp(out[1], F.psi, F.kappa);
+    v2 = e.w_b * decode_lp(out[2], F.psi, F.kappa);
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) {
+    v0 += __shfl_xor(v0, o);
+    v1 += __shfl_xor(v1, o);
+    v2 += __shfl_xor(v2, o);
+  }
+  if (lane == 0 && e.cnt > 0) {
+    float *dst = e.next >= 0 ? a.out_ci + 3 * (size_t)e.next : a.acc_i + 3 * (size_t)e.r;
+    dst[0] = e.ci.x + v0;
+    dst[1] = e.ci.y + v1;
+    dst[2] = e.ci.z + v2;
+  }
 }
 
 template <int P>
@@ -293,58 +423,24 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
   const FieldDev &F = *a.F;
   const int lane = lane_id(), q = lane >> 4, c = lane & 15;
   const int waves = (int)gridDim.x * (WF_THREADS / 64);
-  for (int t = (int)blockIdx.x * (WF_THREADS / 64) + (int)(threadIdx.x >> 6); t < a.n_entries;
-       t += waves) {
-    const int cnt = a.ent_cnt[t];
-    if (cnt == 0) continue;
-    const uint32_t r = a.ent_ray[t];
-    const float g = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
-    const float2 u = a.ent_u[t];
-    const int64_t s = (int64_t)t * WF_SLOTS + c;
-    const bool valid = c < cnt;
-    float pos[8], dir[8];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int lv = 4 * q + k;
-      float2 fp = make_float2(0.0f, 0.0f), fd = make_float2(0.0f, 0.0f);
-      if (lv < F.levels) {
-        if (valid) fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + s);
-        fd = encode_dir_level<P>(F, lv, (double)u.x, (double)u.y);
-      }
-      pos[2 * k] = fp.x;
-      pos[2 * k + 1] = fp.y;
-      dir[2 * k] = fd.x;
-      dir[2 * k + 1] = fd.y;
-    }
-    const float gin = (q == 0) ? g : 0.0f;
+  const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (WF_THREADS / 64) +
+                                                (int)(threadIdx.x >> 6));
+  for (int t = w0; t < a.n_entries; t += waves) {
+    FieldTileIn e;
+    load_tile<P>(a, F, t, q, c, e);
+    if (e.cnt == 0) continue;  // the march kernel stored this ray's sums
+    const float g = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)e.r)].g;
+    const float gin = q == 0 ? g : 0.0f;
     f32x4 out;
     if constexpr (P == P_F32) {
-      out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w), F.hidden, pos, dir, gin);
+      out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w), F.hidden, e.pos, e.dir, gin);
     } else {
       typedef Mma<P> M;
       float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
       out = mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w), F.hidden,
-                             M::pack(pos), M::pack(dir), M::pack(gz));
+                             M::pack(e.pos), M::pack(e.dir), M::pack(gz));
     }
-    // lanes 0..15 hold the decoded output of query c; weight by W and sum in a fixed order
-    float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-    if (q == 0 && valid) {
-      v0 = a.wr[s] * decode_lp(out[0], F.psi, F.kappa);
-      v1 = a.wg[s] * decode_lp(out[1], F.psi, F.kappa);
-      v2 = a.wb[s] * decode_lp(out[2], F.psi, F.kappa);
-    }
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) {
-      v0 += __shfl_xor(v0, o);
-      v1 += __shfl_xor(v1, o);
-      v2 += __shfl_xor(v2, o);
-    }
-    if (lane == 0) {
-      float *ac = a.acc + (size_t)r * 3;
-      ac[0] += v0;
-      ac[1] += v1;
-      ac[2] += v2;
-    }
+    finish_tile(a, F, e, out, lane, q, c);
   }
 }
 
@@ -365,8 +461,9 @@ __global__ void wf_resolve_kernel(WfResolveArgs a) {
   const int64_t per_s = (int64_t)job.tiles * 64;
   f3 C = {0.f, 0.f, 0.f};
   for (int s = 0; s < job.spp; ++s) {
-    const float *ac = a.acc + (size_t)(job.ray_begin + s * per_s + tile * 64 + ln) * 3;
-    C = C + f3{ac[0], ac[1], ac[2]};
+    const size_t r = (size_t)(job.ray_begin + s * per_s + tile * 64 + ln) * 3;
+    C = C + (f3{a.acc_d[r], a.acc_d[r + 1], a.acc_d[r + 2]} +
+             f3{a.acc_i[r], a.acc_i[r + 1], a.acc_i[r + 2]});
   }
   float *o = job.out + (size_t)pi * 3;
   o[0] = C.x * job.inv_spp;
@@ -380,27 +477,27 @@ static hipError_t alloc_n(T *&p, size_t n) {
   return hipMalloc((void **)&p, sizeof(T) * n);
 }
 
+template <typename T>
+static void free_p(T *&p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
 static void free_entries(WfState &w) {
   for (int i = 0; i < 2; ++i) {
-    (void)hipFree(w.list_ray[i]);
-    (void)hipFree(w.list_j[i]);
-    (void)hipFree(w.list_T[i]);
-    w.list_ray[i] = nullptr;
-    w.list_j[i] = nullptr;
-    w.list_T[i] = nullptr;
+    free_p(w.list_ray[i]);
+    free_p(w.list_j[i]);
+    free_p(w.list_T[i]);
+    free_p(w.list_cd[i]);
+    free_p(w.list_ci[i]);
   }
-  (void)hipFree(w.ent_ray);
-  (void)hipFree(w.ent_cnt);
-  (void)hipFree(w.ent_u);
-  w.ent_ray = nullptr;
-  w.ent_cnt = nullptr;
-  w.ent_u = nullptr;
-  for (int i = 0; i < 6; ++i) {
-    (void)hipFree(w.slot[i]);
-    w.slot[i] = nullptr;
-  }
-  (void)hipFree(w.feat);
-  w.feat = nullptr;
+  free_p(w.ent_ray);
+  free_p(w.ent_cnt);
+  free_p(w.ent_next);
+  free_p(w.ent_u);
+  for (int i = 0; i < 6; ++i) free_p(w.slot[i]);
+  free_p(w.feat);
+  free_p(w.dfeat);
   w.ent_cap = 0;
   w.feat_elem = 0;
 }
@@ -415,23 +512,30 @@ static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t fea
       if ((e = alloc_n(w.list_ray[i], entries))) return e;
       if ((e = alloc_n(w.list_j[i], entries))) return e;
       if ((e = alloc_n(w.list_T[i], entries))) return e;
+      if ((e = alloc_n(w.list_cd[i], entries * 3))) return e;
+      if ((e = alloc_n(w.list_ci[i], entries * 3))) return e;
     }
     if ((e = alloc_n(w.ent_ray, entries))) return e;
     if ((e = alloc_n(w.ent_cnt, entries))) return e;
+    if ((e = alloc_n(w.ent_next, entries))) return e;
     if ((e = alloc_n(w.ent_u, entries))) return e;
     for (int i = 0; i < 6; ++i)
       if ((e = alloc_n(w.slot[i], entries * WF_SLOTS))) return e;
     unsigned char *fp = nullptr;
     if ((e = alloc_n(fp, entries * WF_SLOTS * PFN_MAX_LEVELS * feat_bytes))) return e;
     w.feat = fp;
+    fp = nullptr;
+    if ((e = alloc_n(fp, entries * PFN_MAX_LEVELS * feat_bytes))) return e;
+    w.dfeat = fp;
     w.ent_cap = entries;
     w.feat_elem = feat_bytes;
   }
   if (rays * 3 > w.acc_cap) {
-    (void)hipFree(w.acc);
-    w.acc = nullptr;
+    free_p(w.acc_d);
+    free_p(w.acc_i);
     w.acc_cap = 0;
-    if ((e = alloc_n(w.acc, rays * 3))) return e;
+    if ((e = alloc_n(w.acc_d, rays * 3))) return e;
+    if ((e = alloc_n(w.acc_i, rays * 3))) return e;
     w.acc_cap = rays * 3;
   }
   if (!w.count) {
@@ -443,10 +547,11 @@ static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t fea
 
 void wf_release(WfState &w) {
   free_entries(w);
-  (void)hipFree(w.acc);
-  (void)hipFree(w.count);
+  free_p(w.acc_d);
+  free_p(w.acc_i);
+  free_p(w.count);
   if (w.host_count) (void)hipHostFree(w.host_count);
-  (void)hipFree(w.pix_begin);
+  free_p(w.pix_begin);
   w = WfState{};
 }
 
@@ -456,7 +561,7 @@ static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
 }
 
 template <int P>
-static void launch_k23(pfn_context *ctx, const WfEncArgs &e,
+static void launch_k23(pfn_context *ctx, const WfEncArgs &e, const WfDirArgs &dg,
                        const std::vector<std::pair<int, int>> &groups, const WfFieldArgs &f,
                        int field_blocks) {
   const int eb = (int)((e.n_slots + WF_THREADS - 1) / WF_THREADS);
@@ -468,10 +573,30 @@ static void launch_k23(pfn_context *ctx, const WfEncArgs &e,
     hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, ctx->stream, ee);
     timing_end(ctx, ts, TK_WF_ENCODE);
   }
+  {
+    const int ts = timing_begin(ctx);
+    hipLaunchKernelGGL((wf_dir_kernel<P>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
+                       dim3(WF_THREADS), 0, ctx->stream, dg);
+    timing_end(ctx, ts, TK_WF_ENCODE);
+  }
   const int ts = timing_begin(ctx);
   hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
                      (size_t)f.mlp_bytes, ctx->stream, f);
   timing_end(ctx, ts, TK_WF_FIELD);
+}
+
+template <int P>
+static int field_blocks_resident(int mlp_bytes) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field_kernel<P>, WF_THREADS,
+                                                   (size_t)mlp_bytes) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess)
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  return per_cu * cus;
 }
 
 pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
@@ -493,8 +618,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   const size_t fbytes = prec == P_F32 ? 8 : 4;
   PFN_HIP(ctx, wf_reserve(w, entries, (size_t)rays, fbytes));
   if (w.pix_cap < mj.size() + 1) {
-    (void)hipFree(w.pix_begin);
-    w.pix_begin = nullptr;
+    free_p(w.pix_begin);
     w.pix_cap = 0;
     PFN_HIP(ctx, hipMalloc((void **)&w.pix_begin, sizeof(int64_t) * (mj.size() + 1)));
     w.pix_cap = mj.size() + 1;
@@ -509,20 +633,17 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   // level alone
   std::vector<std::pair<int, int>> groups;
   {
-    int l = 0;
+    auto fine = [&](int l) {
+      return !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
+    };
     const int L = fd_host.levels;
+    int l = 0;
     while (l < L) {
-      const bool fine = !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
-      if (fine) {
-        groups.push_back({l, l + 1});
-        ++l;
-      } else {
-        int e = l;
-        while (e < L && !(!((fd_host.pos.dense_mask >> e) & 1u) && fd_host.pos.res[e] >= WF_FINE_RES))
-          ++e;
-        groups.push_back({l, e});
-        l = e;
-      }
+      int e = l + 1;
+      if (!fine(l))
+        while (e < L && !fine(e)) ++e;
+      groups.push_back({l, e});
+      l = e;
     }
   }
 
@@ -531,6 +652,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   a.out_count = w.count;
   a.ent_ray = w.ent_ray;
   a.ent_cnt = w.ent_cnt;
+  a.ent_next = w.ent_next;
   a.ent_u = w.ent_u;
   a.qx = w.slot[0];
   a.qy = w.slot[1];
@@ -538,7 +660,8 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   a.wr = w.slot[3];
   a.wg = w.slot[4];
   a.wb = w.slot[5];
-  a.acc = w.acc;
+  a.acc_d = w.acc_d;
+  a.acc_i = w.acc_i;
 
   WfEncArgs e{};
   e.F = m.fields + slot;
@@ -548,6 +671,12 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   e.qz = w.slot[2];
   e.feat = w.feat;
 
+  WfDirArgs dg{};
+  dg.F = m.fields + slot;
+  dg.ent_cnt = w.ent_cnt;
+  dg.ent_u = w.ent_u;
+  dg.dfeat = w.dfeat;
+
   WfFieldArgs f{};
   f.F = m.fields + slot;
   f.mlp = ctx->fields[slot].mlp_packed[prec];
@@ -556,12 +685,16 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   f.n_jobs = m.n_jobs;
   f.ent_ray = w.ent_ray;
   f.ent_cnt = w.ent_cnt;
-  f.ent_u = w.ent_u;
+  f.ent_next = w.ent_next;
   f.wr = w.slot[3];
   f.wg = w.slot[4];
   f.wb = w.slot[5];
   f.feat = w.feat;
-  f.acc = w.acc;
+  f.dfeat = w.dfeat;
+  f.acc_i = w.acc_i;
+  const int fb_max = prec == P_F32   ? field_blocks_resident<P_F32>(m.mlp_bytes)
+                     : prec == P_BF16 ? field_blocks_resident<P_BF16>(m.mlp_bytes)
+                                      : field_blocks_resident<P_F16>(m.mlp_bytes);
 
   const int tslot = timing_begin(ctx);
   int64_t fresh_next = 0;
@@ -569,12 +702,9 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   while (fresh_next < rays || n_cont > 0) {
     const int n_fresh = (int)std::min<int64_t>((int64_t)entries - n_cont, rays - fresh_next);
     const int n_in = n_cont + n_fresh;
-    a.in_ray = w.list_ray[cur];
-    a.in_j = w.list_j[cur];
-    a.in_T = w.list_T[cur];
-    a.out_ray = w.list_ray[cur ^ 1];
-    a.out_j = w.list_j[cur ^ 1];
-    a.out_T = w.list_T[cur ^ 1];
+    a.in = {w.list_ray[cur], w.list_j[cur], w.list_T[cur], w.list_cd[cur], w.list_ci[cur]};
+    a.out = {w.list_ray[cur ^ 1], w.list_j[cur ^ 1], w.list_T[cur ^ 1], w.list_cd[cur ^ 1],
+             w.list_ci[cur ^ 1]};
     a.n_cont = n_cont;
     a.n_fresh = n_fresh;
     a.fresh_begin = fresh_next;
@@ -592,12 +722,16 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     timing_end(ctx, ts1, TK_WF_MARCH);
     PFN_HIP(ctx, hipGetLastError());
     e.n_slots = (int64_t)n_in * WF_SLOTS;
+    dg.n_entries = n_in;
     f.n_slots = e.n_slots;
     f.n_entries = n_in;
-    const int fb = std::max(1, std::min((n_in + 3) / 4, 256 * 8));
-    if (prec == P_F32) launch_k23<P_F32>(ctx, e, groups, f, fb);
-    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, e, groups, f, fb);
-    else launch_k23<P_F16>(ctx, e, groups, f, fb);
+    f.n_cont = n_cont;
+    f.in_ci = w.list_ci[cur];
+    f.out_ci = w.list_ci[cur ^ 1];
+    const int fb = std::max(1, std::min((n_in + 3) / 4, fb_max));
+    if (prec == P_F32) launch_k23<P_F32>(ctx, e, dg, groups, f, fb);
+    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, e, dg, groups, f, fb);
+    else launch_k23<P_F16>(ctx, e, dg, groups, f, fb);
     PFN_HIP(ctx, hipGetLastError());
     PFN_HIP(ctx, hipMemcpyAsync(w.host_count, w.count, 4, hipMemcpyDeviceToHost, ctx->stream));
     PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -609,7 +743,8 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   ra.jobs = m.jobs;
   ra.n_jobs = m.n_jobs;
   ra.pix_begin = w.pix_begin;
-  ra.acc = w.acc;
+  ra.acc_d = w.acc_d;
+  ra.acc_i = w.acc_i;
   ra.tile_w = m.tile_w;
   ra.tile_h = m.tile_h;
   const int tsr = timing_begin(ctx);
