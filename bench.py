@@ -405,9 +405,18 @@ def matched_rmse(args):
     per_g = {}
     pt_spp = [16, 32, 64, 128, 256]
     for g in (0.4, 0.2):
-        ref = ctx.render_path_traced(cam, args.mr_ref_spp, max_bounces=8, g=g, rr_start=3,
-                                     seed=1000)
-        torch.cuda.synchronize()
+        # the reference: the mean of independent path-traced renders of at most 512 spp each
+        chunk = min(512, args.mr_ref_spp)
+        n_chunks = max(1, args.mr_ref_spp // chunk)
+        ref = torch.zeros_like(out)
+        part = torch.empty_like(out)
+        for c in range(n_chunks):
+            ctx.render_path_traced(cam, chunk, max_bounces=8, g=g, rr_start=3, seed=1000 + c,
+                                   out=part)
+            ref += part
+            torch.cuda.synchronize()
+            log(f"[mr] g={g} reference {(c + 1) * chunk}/{n_chunks * chunk} spp")
+        ref /= n_chunks
         field_ms = timed(lambda: ctx.render_frame(cam, field_rc(g), out), 3)
         e_field = ctx.image_error(out, ref)
         cache_ms = timed(lambda: ctx.render_frame(cam, field_rc(g, INDIRECT_CACHE), out), 3)

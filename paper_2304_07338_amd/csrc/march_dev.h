@@ -13,14 +13,16 @@ __device__ __forceinline__ float4 tri_fetch4(const ushort4 *__restrict__ p, cons
   const float w[8] = {gx * gy * gz,       t.fx * gy * gz,      gx * t.fy * gz,
                       t.fx * t.fy * gz,   gx * gy * t.fz,      t.fx * gy * t.fz,
                       gx * t.fy * t.fz,   t.fx * t.fy * t.fz};
+  // one 8-byte load per texel (four binary16 channels)
+  const uint2 *q = reinterpret_cast<const uint2 *>(p);
   float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    ushort4 v = p[o[k]];
-    acc.x = fmaf(w[k], __half2float(__ushort_as_half(v.x)), acc.x);
-    acc.y = fmaf(w[k], __half2float(__ushort_as_half(v.y)), acc.y);
-    acc.z = fmaf(w[k], __half2float(__ushort_as_half(v.z)), acc.z);
-    acc.w = fmaf(w[k], __half2float(__ushort_as_half(v.w)), acc.w);
+    const uint2 v = q[o[k]];
+    acc.x = fmaf(w[k], __half2float(__ushort_as_half((unsigned short)(v.x & 0xFFFFu))), acc.x);
+    acc.y = fmaf(w[k], __half2float(__ushort_as_half((unsigned short)(v.x >> 16))), acc.y);
+    acc.z = fmaf(w[k], __half2float(__ushort_as_half((unsigned short)(v.y & 0xFFFFu))), acc.z);
+    acc.w = fmaf(w[k], __half2float(__ushort_as_half((unsigned short)(v.y >> 16))), acc.w);
   }
   return acc;
 }
@@ -58,20 +60,24 @@ __device__ __forceinline__ f3 direct_light(const MarchArgs &a, const MarchJob &j
   f3 Ld = {0.0f, 0.0f, 0.0f};
   float4 tl = make_float4(1.f, 1.f, 1.f, 1.f);
   if constexpr (DIRECT == PFN_DIRECT_LIGHT_VOLUME) tl = tri_fetch4(a.lightvol, tri_setup(a.lvg, x));
+  // HG phase (1 - g^2) / (4 pi) * d^(-3/2), d = 1 + g^2 - 2 g mu, and the inverse-square falloff,
+  // all through reciprocal square roots (no divisions in the step loop)
+  const float g = job.g;
+  const float hg_c = (1.0f - g * g) * (0.25f / PFN_PI), hg_a = 1.0f + g * g, hg_b = 2.0f * g;
 #pragma unroll
   for (int l = 0; l < PFN_MAX_LIGHTS; ++l) {
     if (l >= a.n_lights || !((job.light_mask >> l) & 1)) continue;
     f3 p = {a.light_pos[l][0], a.light_pos[l][1], a.light_pos[l][2]};
     f3 v = x - p;
-    float r2 = dot(v, v);
-    float r = sqrtf(r2);
-    float mu = dot(v, wo) / r;
+    float ir = rsqrtf(dot(v, v));  // r > 0 unless a sample falls exactly on a light
+    float mu = dot(v, wo) * ir;
+    float rd = rsqrtf(fmaf(-hg_b, mu, hg_a));
     float T;
     if constexpr (DIRECT == PFN_DIRECT_LIGHT_VOLUME)
       T = l == 0 ? tl.x : l == 1 ? tl.y : l == 2 ? tl.z : tl.w;
     else
       T = shadow_T<VT>(a, tf, x, p, job.step);
-    float k = hg_eval(job.g, mu) * T / r2;
+    float k = hg_c * (rd * rd * rd) * T * (ir * ir);
     Ld = Ld + f3{a.light_int[l][0], a.light_int[l][1], a.light_int[l][2]} * k;
   }
   return Ld;
