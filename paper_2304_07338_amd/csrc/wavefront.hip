@@ -31,6 +31,15 @@
 #define WF_MAX_ENTRIES (1 << 21)     // rays per round
 #define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
 
+// Query slot k of round entry t.  Slots are tiled as [t / 64][k][t % 64]: the 64 rays of a march
+// wave write slot k of 64 consecutive entries, and 16 neighbouring rays' slot k are 64
+// contiguous bytes for the field kernel.
+__host__ __device__ __forceinline__ int64_t wf_slot(int64_t t, int k) {
+  return ((t >> 6) << 10) | ((int64_t)k << 6) | (t & 63);
+}
+// Slots spanned by the first n entries.
+__host__ __device__ __forceinline__ int64_t wf_slots(int64_t n) { return ((n + 63) >> 6) << 10; }
+
 // Rays continued from the previous round: ray id, next step, transmittance and the direct and
 // indirect sums so far (RGB, entry-major).
 struct WfList {
@@ -52,7 +61,7 @@ struct WfArgs {
   int *ent_cnt;
   int *ent_next;      // index of the entry's ray in the out list, or -1 when the ray ended
   float2 *ent_u;
-  // per query slot (entry * WF_SLOTS + k)
+  // per query slot (wf_slot(entry, k))
   float *qx, *qy, *qz, *wr, *wg, *wb;
   float *acc_d, *acc_i;  // per ray sample: final direct and indirect RGB sums
 };
@@ -63,6 +72,7 @@ struct WfEncArgs {
   const float *qx, *qy, *qz;
   void *feat;           // [level][slot]: uint32 (two 16-bit features) or float2 (FP32)
   int64_t n_slots;
+  int n_entries;
   int l0, l1;
 };
 
@@ -164,7 +174,6 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
   int cnt = 0;
   bool finished = !live;
   unsigned n_steps = 0;
-  const size_t slot0 = (size_t)t * WF_SLOTS;
   while (!finished && cnt < WF_SLOTS) {
     f3 W = {0.f, 0.f, 0.f};
     f3 xq = {0.f, 0.f, 0.f};
@@ -196,7 +205,7 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
       }
     }
     if (W.x != 0.f || W.y != 0.f || W.z != 0.f) {
-      const size_t q = slot0 + cnt;
+      const int64_t q = wf_slot(t, cnt);
       a.qx[q] = xq.x;
       a.qy[q] = xq.y;
       a.qz[q] = xq.z;
@@ -316,9 +325,9 @@ template <int P>
 __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   const int64_t s = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
   if (s >= e.n_slots) return;
-  const int64_t t = s / WF_SLOTS;
-  const int c = (int)(s - t * WF_SLOTS);
-  if (c >= e.ent_cnt[t]) return;
+  const int64_t t = ((s >> 10) << 6) | (s & 63);
+  const int c = (int)((s >> 6) & 15);
+  if (t >= e.n_entries || c >= e.ent_cnt[t]) return;
   const FieldDev &F = *e.F;
   const f3 x = clamp01(f3{e.qx[s], e.qy[s], e.qz[s]});
   for (int lv = e.l0; lv < e.l1; ++lv)
@@ -337,110 +346,95 @@ __global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
                   encode_dir_level<P>(F, lv, (double)u.x, (double)u.y));
 }
 
-// Operands of one ray's tile in the field kernel: lane group q, column c.
-struct FieldTileIn {
-  int cnt, next;
-  uint32_t r;
-  f3 ci;
-  float pos[8], dir[8];
-  float w_r, w_g, w_b;
-};
-
-// Loads that depend on the entry index alone, so that all of them are in flight together.
-template <int P>
-__device__ __forceinline__ void load_tile(const WfFieldArgs &a, const FieldDev &F, int t, int q,
-                                          int c, FieldTileIn &e) {
-  e.cnt = 0;
-  e.next = -1;
-  e.r = 0;
-  e.ci = {0.f, 0.f, 0.f};
-  e.w_r = e.w_g = e.w_b = 0.f;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) e.pos[k] = e.dir[k] = 0.0f;
-  if (t >= a.n_entries) return;
-  e.cnt = a.ent_cnt[t];
-  e.next = a.ent_next[t];
-  e.r = a.ent_ray[t];
-  const int64_t s = (int64_t)t * WF_SLOTS + c;
-  if (t < a.n_cont)
-    e.ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int lv = 4 * q + k;
-    float2 fp = make_float2(0.0f, 0.0f), fd = make_float2(0.0f, 0.0f);
-    if (lv < F.levels) {
-      fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + s);
-      fd = load_feat2<P>(a.dfeat, (int64_t)lv * a.n_entries + t);
-    }
-    e.pos[2 * k] = fp.x;
-    e.pos[2 * k + 1] = fp.y;
-    e.dir[2 * k] = fd.x;
-    e.dir[2 * k + 1] = fd.y;
-  }
-  if (q == 0) {
-    e.w_r = a.wr[s];
-    e.w_g = a.wg[s];
-    e.w_b = a.wb[s];
-  }
-  // columns past the ray's count, and rays without queries, hold stale buffer contents
-  const bool valid = c < e.cnt;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    e.pos[k] = valid ? e.pos[k] : 0.0f;
-    e.dir[k] = e.cnt > 0 ? e.dir[k] : 0.0f;
-  }
-}
-
-// Decode, weight by W, sum over the tile's columns in a fixed order, and store the ray's sum.
-__device__ __forceinline__ void finish_tile(const WfFieldArgs &a, const FieldDev &F,
-                                            const FieldTileIn &e, f32x4 out, int lane, int q,
-                                            int c) {
-  float v0 = 0.f, v1 = 0.f, v2 = 0.f;
-  if (q == 0 && c < e.cnt) {
-    v0 = e.w_r * decode_lp(out[0], F.psi, F.kappa);
-    v1 = e.w_g * decode_lp(out[1], F.psi, F.kappa);
-    v2 = e.w_b * decode_lp(out[2], F.psi, F.kappa);
-  }
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) {
-    v0 += __shfl_xor(v0, o);
-    v1 += __shfl_xor(v1, o);
-    v2 += __shfl_xor(v2, o);
-  }
-  if (lane == 0 && e.cnt > 0) {
-    float *dst = e.next >= 0 ? a.out_ci + 3 * (size_t)e.next : a.acc_i + 3 * (size_t)e.r;
-    dst[0] = e.ci.x + v0;
-    dst[1] = e.ci.y + v1;
-    dst[2] = e.ci.z + v2;
-  }
-}
-
+// Field kernel: a wave takes 16 neighbouring rays of the round (entries t0..t0+15, one per
+// matrix-core column) and runs one tile per query index k = 0..15: column c of tile k is query k
+// of ray t0+c.  Lane group q holds levels 4q..4q+3 of its column's features; the direction
+// features of a column's ray are loaded once for all tiles.  Each column accumulates W * L_i of
+// its ray over k in order, in the lanes of group 0.
 template <int P>
 __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
   extern __shared__ __align__(16) unsigned char lds_w[];
   stage_weights(lds_w, a.mlp, a.mlp_bytes);
   __syncthreads();
   const FieldDev &F = *a.F;
-  const int lane = lane_id(), q = lane >> 4, c = lane & 15;
+  const int lane = lane_id(), q = lane >> 4, col = lane & 15;
   const int waves = (int)gridDim.x * (WF_THREADS / 64);
   const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (WF_THREADS / 64) +
                                                 (int)(threadIdx.x >> 6));
-  for (int t = w0; t < a.n_entries; t += waves) {
-    FieldTileIn e;
-    load_tile<P>(a, F, t, q, c, e);
-    if (e.cnt == 0) continue;  // the march kernel stored this ray's sums
-    const float g = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)e.r)].g;
-    const float gin = q == 0 ? g : 0.0f;
-    f32x4 out;
-    if constexpr (P == P_F32) {
-      out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w), F.hidden, e.pos, e.dir, gin);
-    } else {
-      typedef Mma<P> M;
-      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
-      out = mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w), F.hidden,
-                             M::pack(e.pos), M::pack(e.dir), M::pack(gz));
+  const int n_tiles = (a.n_entries + 15) >> 4;
+  for (int rt = w0; rt < n_tiles; rt += waves) {
+    const int t = rt * 16 + col;
+    const bool tv = t < a.n_entries;
+    const int cnt = tv ? a.ent_cnt[t] : 0;
+    int kmax = cnt;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+    if (__builtin_amdgcn_readfirstlane(kmax) == 0) continue;  // the march kernel stored the sums
+    int next = -1;
+    uint32_t r = 0;
+    f3 ci = {0.f, 0.f, 0.f};
+    float gin = 0.0f;
+    float dir[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dir[k] = 0.0f;
+    if (cnt > 0) {
+      next = a.ent_next[t];
+      r = a.ent_ray[t];
+      if (t < a.n_cont)
+        ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
+      if (q == 0) gin = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int lv = 4 * q + k;
+        if (lv < F.levels) {
+          const float2 fd = load_feat2<P>(a.dfeat, (int64_t)lv * a.n_entries + t);
+          dir[2 * k] = fd.x;
+          dir[2 * k + 1] = fd.y;
+        }
+      }
     }
-    finish_tile(a, F, e, out, lane, q, c);
+    f3 S = {0.f, 0.f, 0.f};
+    for (int k = 0; k < kmax; ++k) {
+      // an offset the compiler cannot see through: the weight reads stay inside the loop
+      // instead of being hoisted into (and spilling) registers
+      int wofs = 0;
+      asm volatile("" : "+s"(wofs));
+      const bool valid = k < cnt;
+      const int64_t sl = wf_slot(t, k);
+      float pos[8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int lv = 4 * q + j;
+        float2 fp = make_float2(0.0f, 0.0f);
+        if (valid && lv < F.levels) fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + sl);
+        pos[2 * j] = fp.x;
+        pos[2 * j + 1] = fp.y;
+      }
+      f3 W = {0.f, 0.f, 0.f};
+      if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
+      f32x4 out;
+      if constexpr (P == P_F32) {
+        out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w) + wofs, F.hidden, pos, dir,
+                                gin);
+      } else {
+        typedef Mma<P> M;
+        float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+        out = mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w) + wofs, F.hidden,
+                               M::pack(pos), M::pack(dir), M::pack(gz));
+      }
+      // lanes 0..15 hold the output of column `col`
+      if (q == 0 && valid) {
+        S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+        S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+        S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+      }
+    }
+    if (q == 0 && cnt > 0) {
+      float *dst = next >= 0 ? a.out_ci + 3 * (size_t)next : a.acc_i + 3 * (size_t)r;
+      dst[0] = ci.x + S.x;
+      dst[1] = ci.y + S.y;
+      dst[2] = ci.z + S.z;
+    }
   }
 }
 
@@ -519,10 +513,11 @@ static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t fea
     if ((e = alloc_n(w.ent_cnt, entries))) return e;
     if ((e = alloc_n(w.ent_next, entries))) return e;
     if ((e = alloc_n(w.ent_u, entries))) return e;
+    const size_t slots = (size_t)wf_slots((int64_t)entries);
     for (int i = 0; i < 6; ++i)
-      if ((e = alloc_n(w.slot[i], entries * WF_SLOTS))) return e;
+      if ((e = alloc_n(w.slot[i], slots))) return e;
     unsigned char *fp = nullptr;
-    if ((e = alloc_n(fp, entries * WF_SLOTS * PFN_MAX_LEVELS * feat_bytes))) return e;
+    if ((e = alloc_n(fp, slots * PFN_MAX_LEVELS * feat_bytes))) return e;
     w.feat = fp;
     fp = nullptr;
     if ((e = alloc_n(fp, entries * PFN_MAX_LEVELS * feat_bytes))) return e;
@@ -721,14 +716,15 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     }
     timing_end(ctx, ts1, TK_WF_MARCH);
     PFN_HIP(ctx, hipGetLastError());
-    e.n_slots = (int64_t)n_in * WF_SLOTS;
+    e.n_slots = wf_slots(n_in);
+    e.n_entries = n_in;
     dg.n_entries = n_in;
     f.n_slots = e.n_slots;
     f.n_entries = n_in;
     f.n_cont = n_cont;
     f.in_ci = w.list_ci[cur];
     f.out_ci = w.list_ci[cur ^ 1];
-    const int fb = std::max(1, std::min((n_in + 3) / 4, fb_max));
+    const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));
     if (prec == P_F32) launch_k23<P_F32>(ctx, e, dg, groups, f, fb);
     else if (prec == P_BF16) launch_k23<P_BF16>(ctx, e, dg, groups, f, fb);
     else launch_k23<P_F16>(ctx, e, dg, groups, f, fb);
