@@ -66,7 +66,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=80, help="lattice side of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-job launch")
-    ap.add_argument("--strategy", default="auto", choices=["auto", "fused", "wavefront"],
+    ap.add_argument("--strategy", default="auto", choices=["auto", "fused", "wavefront", "wavefront_serial"],
                     help="form of the field-lit render")
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--matched-rmse", action="store_true",

@@ -244,10 +244,19 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  *     level-major position-encoding kernels (each fine hashed level alone, so that its table
  *     stays in L2) and a matrix-core field kernel per 16-query ray tile; needs every job of the
  *     call to read one field slot and no graph capture, else the fused kernel runs;
+ *     the march kernel of the next round runs on the context's stream while this round's
+ *     encoding and field kernels run on a second stream the library owns (default priority);
+ *   PFN_STRATEGY_WAVEFRONT_SERIAL: the same rounds, all on the context's stream;
  *   PFN_STRATEGY_AUTO (default): the wavefront form wherever it applies.
- * Device buffers of the wavefront form (about 1.5 KB per ray of a round, at most 2^21 rays per
- * round, plus 12 B per ray sample of the frame) are kept in the context and grown on demand. */
-typedef enum { PFN_STRATEGY_AUTO = 0, PFN_STRATEGY_FUSED = 1, PFN_STRATEGY_WAVEFRONT = 2 } pfn_strategy;
+ * Device buffers of the wavefront form (two sets of about 1.5 KB per ray of a round, at most 2^21
+ * rays per round, plus 24 B per ray sample of the frame) are kept in the context and grown on
+ * demand.  Both wavefront variants give bit-identical images. */
+typedef enum {
+  PFN_STRATEGY_AUTO = 0,
+  PFN_STRATEGY_FUSED = 1,
+  PFN_STRATEGY_WAVEFRONT = 2,
+  PFN_STRATEGY_WAVEFRONT_SERIAL = 3
+} pfn_strategy;
 pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy);
 /* Autotuner: time every tile shape / block arrangement / launch mode on this batch (iters
  * launches each), keep the fastest for the context and return it (cached per batch shape). */

@@ -66,7 +66,12 @@ static void timing_collect(pfn_context *ctx) {
 
 // Opens an event pair on the context's stream before a launch; the host does not wait here.
 // Returns the pair's slot (-1 when timing is off); pairs may nest.
-int timing_begin(pfn_context *ctx) {
+int timing_begin(pfn_context *ctx) { return timing_begin_on(ctx, ctx->stream); }
+void timing_end(pfn_context *ctx, int slot, int kernel) {
+  timing_end_on(ctx, slot, kernel, ctx->stream);
+}
+
+int timing_begin_on(pfn_context *ctx, hipStream_t stream) {
   if (!ctx->timing) return -1;
   if (ctx->ev_pending >= 512) timing_collect(ctx);
   int i = ctx->ev_pending;
@@ -76,16 +81,16 @@ int timing_begin(pfn_context *ctx) {
     ctx->ev_pool.push_back(e);
     if (ctx->ev_kernel.size() * 2 < ctx->ev_pool.size()) ctx->ev_kernel.push_back(-1);
   }
-  if (hipEventRecord(ctx->ev_pool[2 * i], ctx->stream) != hipSuccess) return -1;
+  if (hipEventRecord(ctx->ev_pool[2 * i], stream) != hipSuccess) return -1;
   ctx->ev_kernel[i] = -1;
   ctx->ev_pending = i + 1;
   ctx->ev_open += 1;
   return i;
 }
 
-void timing_end(pfn_context *ctx, int slot, int kernel) {
+void timing_end_on(pfn_context *ctx, int slot, int kernel, hipStream_t stream) {
   if (slot < 0 || !ctx->timing) return;
-  (void)hipEventRecord(ctx->ev_pool[2 * slot + 1], ctx->stream);
+  (void)hipEventRecord(ctx->ev_pool[2 * slot + 1], stream);
   ctx->ev_kernel[slot] = kernel;
   ctx->ev_open -= 1;
 }
@@ -699,7 +704,8 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
       if (jobs[i].params.field_slot != wf_slot) wf_slot = -1;
   }
   if (wf_slot >= 0) {
-    pfn_status st = run_wavefront(ctx, a, mj, p0.direct, prec, wf_slot, fd[wf_slot]);
+    pfn_status st = run_wavefront(ctx, a, mj, p0.direct, prec, wf_slot, fd[wf_slot],
+                                  ctx->strategy != PFN_STRATEGY_WAVEFRONT_SERIAL);
     if (st) return st;
   } else if (ctx->use_graph) {
     // replay a captured launch with the same arguments (the job table, field descriptors and
@@ -810,8 +816,8 @@ extern "C" pfn_status pfn_timing_reset(pfn_context *ctx) {
 extern "C" pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy) {
   CHECK_CTX(ctx);
   ARG(strategy == PFN_STRATEGY_AUTO || strategy == PFN_STRATEGY_FUSED ||
-          strategy == PFN_STRATEGY_WAVEFRONT,
-      "strategy is PFN_STRATEGY_AUTO, PFN_STRATEGY_FUSED or PFN_STRATEGY_WAVEFRONT");
+          strategy == PFN_STRATEGY_WAVEFRONT || strategy == PFN_STRATEGY_WAVEFRONT_SERIAL,
+      "strategy is PFN_STRATEGY_AUTO, _FUSED, _WAVEFRONT or _WAVEFRONT_SERIAL");
   ctx->strategy = strategy;
   return PFN_OK;
 }

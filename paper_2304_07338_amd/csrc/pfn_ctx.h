@@ -46,13 +46,9 @@ struct MarchGraph {
   hipGraphExec_t exec = nullptr;
 };
 
-// Buffers of the wavefront render (rays per round, query slots, features, per-ray sums).
-struct WfState {
-  uint32_t *list_ray[2] = {nullptr, nullptr};  // continuing rays, ping-pong between rounds
-  int *list_j[2] = {nullptr, nullptr};
-  float *list_T[2] = {nullptr, nullptr};
-  float *list_cd[2] = {nullptr, nullptr};      // carried direct and indirect RGB sums
-  float *list_ci[2] = {nullptr, nullptr};
+// Buffers of one round of the wavefront render (two sets, so that the march kernel of the next
+// round can run while the encoding and field kernels of this one do).
+struct WfRound {
   uint32_t *ent_ray = nullptr;
   int *ent_cnt = nullptr;
   int *ent_next = nullptr;
@@ -60,11 +56,23 @@ struct WfState {
   float *slot[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // x y z, W rgb
   void *feat = nullptr;   // position features [level][slot]
   void *dfeat = nullptr;  // direction features [level][entry]
-  float *acc_d = nullptr, *acc_i = nullptr;  // final sums per ray sample
-  unsigned *count = nullptr;       // device counter of continuing rays
-  unsigned *host_count = nullptr;  // pinned copy
+  unsigned *count = nullptr;  // continuing rays appended by the round's march kernel
+};
+
+// Buffers of the wavefront render, kept in the context and grown on demand.
+struct WfState {
+  WfRound rb[2];
+  uint32_t *list_ray[2] = {nullptr, nullptr};  // continuing rays, ping-pong between rounds
+  int *list_j[2] = {nullptr, nullptr};
+  float *list_T[2] = {nullptr, nullptr};
+  float *list_cd[2] = {nullptr, nullptr};      // carried direct and indirect RGB sums
+  float *list_ci[2] = {nullptr, nullptr};
+  float *acc_d = nullptr, *acc_i = nullptr;    // final sums per ray sample
+  unsigned *host_count = nullptr;              // pinned copies of the round counters
   int64_t *pix_begin = nullptr;
   size_t pix_cap = 0, ent_cap = 0, feat_elem = 0, acc_cap = 0;
+  hipStream_t side = nullptr;                  // encoding and field kernels
+  hipEvent_t ev_march[2] = {nullptr, nullptr}, ev_field[2] = {nullptr, nullptr}, ev_done = nullptr;
 };
 
 #define PFN_TIMED_KERNELS 16
@@ -165,10 +173,12 @@ pfn_status pfn_hip(pfn_context *ctx, hipError_t e, const char *what);
 
 pfn_status ensure_scratch(pfn_context *ctx, size_t bytes);
 pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
-                         int direct, int prec, int slot, const FieldDev &fd_host);
+                         int direct, int prec, int slot, const FieldDev &fd_host, bool overlap);
 void wf_release(WfState &w);
 int timing_begin(pfn_context *ctx);
 void timing_end(pfn_context *ctx, int slot, int kernel);
+int timing_begin_on(pfn_context *ctx, hipStream_t stream);
+void timing_end_on(pfn_context *ctx, int slot, int kernel, hipStream_t stream);
 
 // Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,

@@ -30,6 +30,9 @@
 #define WF_SLOTS 16                  // queries per ray per round: one matrix-core tile
 #define WF_MAX_ENTRIES (1 << 21)     // rays per round
 #define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
+#ifndef WF_GROUP_BYTES
+#define WF_GROUP_BYTES (64u << 20)   // table bytes the coarse levels of one encoding launch span
+#endif
 
 // Query slot k of round entry t.  Slots are tiled as [t / 64][k][t % 64]: the 64 rays of a march
 // wave write slot k of 64 consecutive entries, and 16 neighbouring rays' slot k are 64
@@ -59,7 +62,7 @@ struct WfArgs {
   // per entry of this round
   uint32_t *ent_ray;
   int *ent_cnt;
-  int *ent_next;      // index of the entry's ray in the out list, or -1 when the ray ended
+  int *ent_next;      // the ray's index in the out list; -1: the ray ended; -2: no pixel
   float2 *ent_u;
   // per query slot (wf_slot(entry, k))
   float *qx, *qy, *qz, *wr, *wg, *wb;
@@ -124,7 +127,7 @@ __device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, in
 // One ray of the round (see wf_march_kernel); `job` is uniform across the calling lanes.
 template <typename VT, int DIRECT>
 __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, const MarchJob &job,
-                                            int t, bool active, bool fresh, uint32_t r, int j,
+                                            int t, bool active, uint32_t r, int j,
                                             float T, f3 Cd) {
   const int lane = lane_id();
   int px = 0, py = 0, s = 0;
@@ -237,7 +240,7 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
   if (active) {
     a.ent_cnt[t] = pixel_ok ? cnt : 0;
     a.ent_ray[t] = r;
-    a.ent_next[t] = next;
+    a.ent_next[t] = pixel_ok ? next : -2;
     a.ent_u[t] = make_float2(u0, u1);
   }
   if (pixel_ok && !cont) {
@@ -245,14 +248,6 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
     ad[0] = Cd.x;
     ad[1] = Cd.y;
     ad[2] = Cd.z;
-    if (cnt == 0) {  // no field tile this round: the indirect sum is final as carried
-      float *ai = a.acc_i + (size_t)r * 3;
-      f3 ci = {0.f, 0.f, 0.f};
-      if (!fresh) ci = {a.in.ci[3 * (size_t)t], a.in.ci[3 * (size_t)t + 1], a.in.ci[3 * (size_t)t + 2]};
-      ai[0] = ci.x;
-      ai[1] = ci.y;
-      ai[2] = ci.z;
-    }
   }
   if (pixel_ok && a.m.counters) {
     atomicAdd(&a.m.counters[0], (unsigned long long)n_steps);
@@ -294,7 +289,7 @@ __global__ __launch_bounds__(WF_THREADS) void wf_march_kernel(WfArgs a) {
   for (bool pending = true; pending;) {
     const int jc = __builtin_amdgcn_readfirstlane(ji);
     if (ji == jc) {
-      march_entry<VT, DIRECT>(a, tf, a.m.jobs[jc], t, active, fresh, r, j, T, Cd);
+      march_entry<VT, DIRECT>(a, tf, a.m.jobs[jc], t, active, r, j, T, Cd);
       pending = false;
     }
   }
@@ -366,22 +361,23 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
     const int t = rt * 16 + col;
     const bool tv = t < a.n_entries;
     const int cnt = tv ? a.ent_cnt[t] : 0;
+    const int next = tv ? a.ent_next[t] : -2;
     int kmax = cnt;
 #pragma unroll
     for (int o = 8; o >= 1; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
-    if (__builtin_amdgcn_readfirstlane(kmax) == 0) continue;  // the march kernel stored the sums
-    int next = -1;
+    kmax = __builtin_amdgcn_readfirstlane(kmax);
     uint32_t r = 0;
     f3 ci = {0.f, 0.f, 0.f};
+    if (next != -2) {
+      r = a.ent_ray[t];
+      if (t < a.n_cont)
+        ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
+    }
     float gin = 0.0f;
     float dir[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) dir[k] = 0.0f;
     if (cnt > 0) {
-      next = a.ent_next[t];
-      r = a.ent_ray[t];
-      if (t < a.n_cont)
-        ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
       if (q == 0) gin = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -429,7 +425,9 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
         S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
       }
     }
-    if (q == 0 && cnt > 0) {
+    // continuing rays carry the sum to the next round; ended rays (also those without a query
+    // this round) store it
+    if (q == 0 && next != -2) {
       float *dst = next >= 0 ? a.out_ci + 3 * (size_t)next : a.acc_i + 3 * (size_t)r;
       dst[0] = ci.x + S.x;
       dst[1] = ci.y + S.y;
@@ -484,14 +482,15 @@ static void free_entries(WfState &w) {
     free_p(w.list_T[i]);
     free_p(w.list_cd[i]);
     free_p(w.list_ci[i]);
+    WfRound &b = w.rb[i];
+    free_p(b.ent_ray);
+    free_p(b.ent_cnt);
+    free_p(b.ent_next);
+    free_p(b.ent_u);
+    for (int k = 0; k < 6; ++k) free_p(b.slot[k]);
+    free_p(b.feat);
+    free_p(b.dfeat);
   }
-  free_p(w.ent_ray);
-  free_p(w.ent_cnt);
-  free_p(w.ent_next);
-  free_p(w.ent_u);
-  for (int i = 0; i < 6; ++i) free_p(w.slot[i]);
-  free_p(w.feat);
-  free_p(w.dfeat);
   w.ent_cap = 0;
   w.feat_elem = 0;
 }
@@ -502,26 +501,27 @@ static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t fea
   hipError_t e = hipSuccess;
   if (entries > w.ent_cap || feat_bytes > w.feat_elem) {
     free_entries(w);
+    const size_t slots = (size_t)wf_slots((int64_t)entries);
     for (int i = 0; i < 2; ++i) {
       if ((e = alloc_n(w.list_ray[i], entries))) return e;
       if ((e = alloc_n(w.list_j[i], entries))) return e;
       if ((e = alloc_n(w.list_T[i], entries))) return e;
       if ((e = alloc_n(w.list_cd[i], entries * 3))) return e;
       if ((e = alloc_n(w.list_ci[i], entries * 3))) return e;
+      WfRound &b = w.rb[i];
+      if ((e = alloc_n(b.ent_ray, entries))) return e;
+      if ((e = alloc_n(b.ent_cnt, entries))) return e;
+      if ((e = alloc_n(b.ent_next, entries))) return e;
+      if ((e = alloc_n(b.ent_u, entries))) return e;
+      for (int k = 0; k < 6; ++k)
+        if ((e = alloc_n(b.slot[k], slots))) return e;
+      unsigned char *fp = nullptr;
+      if ((e = alloc_n(fp, slots * PFN_MAX_LEVELS * feat_bytes))) return e;
+      b.feat = fp;
+      fp = nullptr;
+      if ((e = alloc_n(fp, entries * PFN_MAX_LEVELS * feat_bytes))) return e;
+      b.dfeat = fp;
     }
-    if ((e = alloc_n(w.ent_ray, entries))) return e;
-    if ((e = alloc_n(w.ent_cnt, entries))) return e;
-    if ((e = alloc_n(w.ent_next, entries))) return e;
-    if ((e = alloc_n(w.ent_u, entries))) return e;
-    const size_t slots = (size_t)wf_slots((int64_t)entries);
-    for (int i = 0; i < 6; ++i)
-      if ((e = alloc_n(w.slot[i], slots))) return e;
-    unsigned char *fp = nullptr;
-    if ((e = alloc_n(fp, slots * PFN_MAX_LEVELS * feat_bytes))) return e;
-    w.feat = fp;
-    fp = nullptr;
-    if ((e = alloc_n(fp, entries * PFN_MAX_LEVELS * feat_bytes))) return e;
-    w.dfeat = fp;
     w.ent_cap = entries;
     w.feat_elem = feat_bytes;
   }
@@ -533,20 +533,36 @@ static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t fea
     if ((e = alloc_n(w.acc_i, rays * 3))) return e;
     w.acc_cap = rays * 3;
   }
-  if (!w.count) {
-    if ((e = hipMalloc((void **)&w.count, 16))) return e;
-    if ((e = hipHostMalloc((void **)&w.host_count, 16, hipHostMallocDefault))) return e;
+  for (int i = 0; i < 2; ++i)
+    if (!w.rb[i].count && (e = hipMalloc((void **)&w.rb[i].count, 16))) return e;
+  if (!w.host_count && (e = hipHostMalloc((void **)&w.host_count, 16, hipHostMallocDefault)))
+    return e;
+  if (!w.side) {
+    // default priority, and not synchronising with the null stream
+    if ((e = hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking))) return e;
+    for (int i = 0; i < 2; ++i) {
+      if ((e = hipEventCreateWithFlags(&w.ev_march[i], hipEventDisableTiming))) return e;
+      if ((e = hipEventCreateWithFlags(&w.ev_field[i], hipEventDisableTiming))) return e;
+    }
+    if ((e = hipEventCreateWithFlags(&w.ev_done, hipEventDisableTiming))) return e;
   }
   return hipSuccess;
 }
 
 void wf_release(WfState &w) {
+  if (w.side) (void)hipStreamSynchronize(w.side);
   free_entries(w);
   free_p(w.acc_d);
   free_p(w.acc_i);
-  free_p(w.count);
+  for (int i = 0; i < 2; ++i) free_p(w.rb[i].count);
   if (w.host_count) (void)hipHostFree(w.host_count);
   free_p(w.pix_begin);
+  for (int i = 0; i < 2; ++i) {
+    if (w.ev_march[i]) (void)hipEventDestroy(w.ev_march[i]);
+    if (w.ev_field[i]) (void)hipEventDestroy(w.ev_field[i]);
+  }
+  if (w.ev_done) (void)hipEventDestroy(w.ev_done);
+  if (w.side) (void)hipStreamDestroy(w.side);
   w = WfState{};
 }
 
@@ -556,7 +572,7 @@ static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
 }
 
 template <int P>
-static void launch_k23(pfn_context *ctx, const WfEncArgs &e, const WfDirArgs &dg,
+static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, const WfDirArgs &dg,
                        const std::vector<std::pair<int, int>> &groups, const WfFieldArgs &f,
                        int field_blocks) {
   const int eb = (int)((e.n_slots + WF_THREADS - 1) / WF_THREADS);
@@ -564,20 +580,20 @@ static void launch_k23(pfn_context *ctx, const WfEncArgs &e, const WfDirArgs &dg
     WfEncArgs ee = e;
     ee.l0 = g.first;
     ee.l1 = g.second;
-    const int ts = timing_begin(ctx);
-    hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, ctx->stream, ee);
-    timing_end(ctx, ts, TK_WF_ENCODE);
+    const int ts = timing_begin_on(ctx, st);
+    hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
+    timing_end_on(ctx, ts, TK_WF_ENCODE, st);
   }
   {
-    const int ts = timing_begin(ctx);
+    const int ts = timing_begin_on(ctx, st);
     hipLaunchKernelGGL((wf_dir_kernel<P>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
-                       dim3(WF_THREADS), 0, ctx->stream, dg);
-    timing_end(ctx, ts, TK_WF_ENCODE);
+                       dim3(WF_THREADS), 0, st, dg);
+    timing_end_on(ctx, ts, TK_WF_ENCODE, st);
   }
-  const int ts = timing_begin(ctx);
+  const int ts = timing_begin_on(ctx, st);
   hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
-                     (size_t)f.mlp_bytes, ctx->stream, f);
-  timing_end(ctx, ts, TK_WF_FIELD);
+                     (size_t)f.mlp_bytes, st, f);
+  timing_end_on(ctx, ts, TK_WF_FIELD, st);
 }
 
 template <int P>
@@ -594,8 +610,13 @@ static int field_blocks_resident(int mlp_bytes) {
   return per_cu * cus;
 }
 
+// Rounds of the wavefront render.  The march kernel of round r runs on the context's stream;
+// the encoding and field kernels of round r run on a side stream once the march kernel has
+// finished, while the march kernel of round r+1 (which only needs the list of continuing rays)
+// already runs on the context's stream.  Round r+2 reuses round r's buffers, so its march
+// kernel waits for round r's field kernel.  With `overlap` off the side stream is not used.
 pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
-                         int direct, int prec, int slot, const FieldDev &fd_host) {
+                         int direct, int prec, int slot, const FieldDev &fd_host, bool overlap) {
   WfState &w = ctx->wf;
   // ray layout and pixel offsets of the jobs
   int64_t rays = 0, pixels = 0;
@@ -628,112 +649,134 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   // level alone
   std::vector<std::pair<int, int>> groups;
   {
+    const FieldSlot &fs = ctx->fields[slot];
+    const int L = fd_host.levels;
     auto fine = [&](int l) {
       return !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
     };
-    const int L = fd_host.levels;
+    auto bytes = [&](int l) {
+      const size_t end = l + 1 < L ? fd_host.pos.off[l + 1] : fs.pos_entries;
+      return (end - fd_host.pos.off[l]) * fbytes;
+    };
     int l = 0;
     while (l < L) {
       int e = l + 1;
-      if (!fine(l))
-        while (e < L && !fine(e)) ++e;
+      if (!fine(l)) {
+        size_t b = bytes(l);
+        while (e < L && !fine(e) && b + bytes(e) <= WF_GROUP_BYTES) b += bytes(e++);
+      }
       groups.push_back({l, e});
       l = e;
     }
   }
-
-  WfArgs a{};
-  a.m = m;
-  a.out_count = w.count;
-  a.ent_ray = w.ent_ray;
-  a.ent_cnt = w.ent_cnt;
-  a.ent_next = w.ent_next;
-  a.ent_u = w.ent_u;
-  a.qx = w.slot[0];
-  a.qy = w.slot[1];
-  a.qz = w.slot[2];
-  a.wr = w.slot[3];
-  a.wg = w.slot[4];
-  a.wb = w.slot[5];
-  a.acc_d = w.acc_d;
-  a.acc_i = w.acc_i;
-
-  WfEncArgs e{};
-  e.F = m.fields + slot;
-  e.ent_cnt = w.ent_cnt;
-  e.qx = w.slot[0];
-  e.qy = w.slot[1];
-  e.qz = w.slot[2];
-  e.feat = w.feat;
-
-  WfDirArgs dg{};
-  dg.F = m.fields + slot;
-  dg.ent_cnt = w.ent_cnt;
-  dg.ent_u = w.ent_u;
-  dg.dfeat = w.dfeat;
-
-  WfFieldArgs f{};
-  f.F = m.fields + slot;
-  f.mlp = ctx->fields[slot].mlp_packed[prec];
-  f.mlp_bytes = m.mlp_bytes;
-  f.jobs = m.jobs;
-  f.n_jobs = m.n_jobs;
-  f.ent_ray = w.ent_ray;
-  f.ent_cnt = w.ent_cnt;
-  f.ent_next = w.ent_next;
-  f.wr = w.slot[3];
-  f.wg = w.slot[4];
-  f.wb = w.slot[5];
-  f.feat = w.feat;
-  f.dfeat = w.dfeat;
-  f.acc_i = w.acc_i;
   const int fb_max = prec == P_F32   ? field_blocks_resident<P_F32>(m.mlp_bytes)
                      : prec == P_BF16 ? field_blocks_resident<P_BF16>(m.mlp_bytes)
                                       : field_blocks_resident<P_F16>(m.mlp_bytes);
+  hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream;
 
   const int tslot = timing_begin(ctx);
   int64_t fresh_next = 0;
   int n_cont = 0, cur = 0;
-  while (fresh_next < rays || n_cont > 0) {
+  for (int r = 0; fresh_next < rays || n_cont > 0; ++r) {
+    const int p = r & 1;
+    WfRound &b = w.rb[p];
     const int n_fresh = (int)std::min<int64_t>((int64_t)entries - n_cont, rays - fresh_next);
     const int n_in = n_cont + n_fresh;
+
+    WfArgs a{};
+    a.m = m;
     a.in = {w.list_ray[cur], w.list_j[cur], w.list_T[cur], w.list_cd[cur], w.list_ci[cur]};
     a.out = {w.list_ray[cur ^ 1], w.list_j[cur ^ 1], w.list_T[cur ^ 1], w.list_cd[cur ^ 1],
              w.list_ci[cur ^ 1]};
     a.n_cont = n_cont;
     a.n_fresh = n_fresh;
     a.fresh_begin = fresh_next;
-    PFN_HIP(ctx, hipMemsetAsync(w.count, 0, 4, ctx->stream));
+    a.out_count = b.count;
+    a.ent_ray = b.ent_ray;
+    a.ent_cnt = b.ent_cnt;
+    a.ent_next = b.ent_next;
+    a.ent_u = b.ent_u;
+    a.qx = b.slot[0];
+    a.qy = b.slot[1];
+    a.qz = b.slot[2];
+    a.wr = b.slot[3];
+    a.wg = b.slot[4];
+    a.wb = b.slot[5];
+    a.acc_d = w.acc_d;
+    a.acc_i = w.acc_i;
+
+    // march kernel of round r: its buffers were last read by round r-2's field kernel
+    if (overlap && r >= 2) PFN_HIP(ctx, hipStreamWaitEvent(sa, w.ev_field[p], 0));
+    PFN_HIP(ctx, hipMemsetAsync(b.count, 0, 4, sa));
     const int needed = (n_in + WF_THREADS - 1) / WF_THREADS;
     const int k1_blocks = ((needed + 7) / 8) * 8;
-    const int ts1 = timing_begin(ctx);
+    const int ts1 = timing_begin_on(ctx, sa);
     if (ctx->vol_dtype == PFN_F16) {
-      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<__half, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, ctx->stream);
-      else launch_k1<__half, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, ctx->stream);
+      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<__half, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, sa);
+      else launch_k1<__half, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, sa);
     } else {
-      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<float, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, ctx->stream);
-      else launch_k1<float, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, ctx->stream);
+      if (direct == PFN_DIRECT_LIGHT_VOLUME) launch_k1<float, PFN_DIRECT_LIGHT_VOLUME>(a, k1_blocks, sa);
+      else launch_k1<float, PFN_DIRECT_SHADOW_RAYS>(a, k1_blocks, sa);
     }
-    timing_end(ctx, ts1, TK_WF_MARCH);
+    timing_end_on(ctx, ts1, TK_WF_MARCH, sa);
     PFN_HIP(ctx, hipGetLastError());
+    PFN_HIP(ctx, hipMemcpyAsync(w.host_count + p, b.count, 4, hipMemcpyDeviceToHost, sa));
+    PFN_HIP(ctx, hipEventRecord(w.ev_march[p], sa));
+
+    // encoding and field kernels of round r
+    WfEncArgs e{};
+    e.F = m.fields + slot;
+    e.ent_cnt = b.ent_cnt;
+    e.qx = b.slot[0];
+    e.qy = b.slot[1];
+    e.qz = b.slot[2];
+    e.feat = b.feat;
     e.n_slots = wf_slots(n_in);
     e.n_entries = n_in;
+    WfDirArgs dg{};
+    dg.F = m.fields + slot;
+    dg.ent_cnt = b.ent_cnt;
+    dg.ent_u = b.ent_u;
+    dg.dfeat = b.dfeat;
     dg.n_entries = n_in;
+    WfFieldArgs f{};
+    f.F = m.fields + slot;
+    f.mlp = ctx->fields[slot].mlp_packed[prec];
+    f.mlp_bytes = m.mlp_bytes;
+    f.jobs = m.jobs;
+    f.n_jobs = m.n_jobs;
+    f.ent_ray = b.ent_ray;
+    f.ent_cnt = b.ent_cnt;
+    f.ent_next = b.ent_next;
+    f.wr = b.slot[3];
+    f.wg = b.slot[4];
+    f.wb = b.slot[5];
+    f.feat = b.feat;
+    f.dfeat = b.dfeat;
+    f.acc_i = w.acc_i;
     f.n_slots = e.n_slots;
     f.n_entries = n_in;
     f.n_cont = n_cont;
     f.in_ci = w.list_ci[cur];
     f.out_ci = w.list_ci[cur ^ 1];
     const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));
-    if (prec == P_F32) launch_k23<P_F32>(ctx, e, dg, groups, f, fb);
-    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, e, dg, groups, f, fb);
-    else launch_k23<P_F16>(ctx, e, dg, groups, f, fb);
+    if (overlap) PFN_HIP(ctx, hipStreamWaitEvent(sb, w.ev_march[p], 0));
+    if (prec == P_F32) launch_k23<P_F32>(ctx, sb, e, dg, groups, f, fb);
+    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, sb, e, dg, groups, f, fb);
+    else launch_k23<P_F16>(ctx, sb, e, dg, groups, f, fb);
     PFN_HIP(ctx, hipGetLastError());
-    PFN_HIP(ctx, hipMemcpyAsync(w.host_count, w.count, 4, hipMemcpyDeviceToHost, ctx->stream));
-    PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    PFN_HIP(ctx, hipEventRecord(w.ev_field[p], sb));
+
+    // the next round needs the number of continuing rays
+    PFN_HIP(ctx, hipEventSynchronize(w.ev_march[p]));
     fresh_next += n_fresh;
-    n_cont = (int)w.host_count[0];
+    n_cont = (int)w.host_count[p];
     cur ^= 1;
+  }
+  // the resolve reads every ray's final sums: after the last field kernel
+  if (overlap) {
+    PFN_HIP(ctx, hipEventRecord(w.ev_done, sb));
+    PFN_HIP(ctx, hipStreamWaitEvent(sa, w.ev_done, 0));
   }
   WfResolveArgs ra{};
   ra.jobs = m.jobs;
@@ -744,8 +787,8 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   ra.tile_w = m.tile_w;
   ra.tile_h = m.tile_h;
   const int tsr = timing_begin(ctx);
-  hipLaunchKernelGGL(wf_resolve_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0,
-                     ctx->stream, ra);
+  hipLaunchKernelGGL(wf_resolve_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0, sa,
+                     ra);
   timing_end(ctx, tsr, TK_WF_RESOLVE);
   PFN_HIP(ctx, hipGetLastError());
   timing_end(ctx, tslot, TK_MARCH);

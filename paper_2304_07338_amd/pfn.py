@@ -17,7 +17,7 @@ from ._ffi import (DIRECT_LIGHT_VOLUME, DIRECT_SHADOW_RAYS, INDIRECT_CACHE, INDI
                    INDIRECT_NONE, PFN_BF16, PFN_F16, PFN_F32)
 
 DTYPES = {"f32": PFN_F32, "f16": PFN_F16, "bf16": PFN_BF16}
-STRATEGIES = {"auto": 0, "fused": 1, "wavefront": 2}
+STRATEGIES = {"auto": 0, "fused": 1, "wavefront": 2, "wavefront_serial": 3}
 
 
 class PfnError(RuntimeError):
@@ -342,7 +342,7 @@ class Context:
         self._ok(self.lib.pfn_set_launch_mode(self.h, persistent_per_cu, int(use_graph)))
 
     def set_render_strategy(self, strategy: str = "auto"):
-        """"auto", "fused" or "wavefront" (field-lit frames)."""
+        """"auto", "fused", "wavefront" or "wavefront_serial" (field-lit frames)."""
         self._ok(self.lib.pfn_set_render_strategy(self.h, STRATEGIES[strategy]))
 
     def render_path_traced(self, cam, spp: int, max_bounces: int = 8, g: float = 0.0,

@@ -130,3 +130,23 @@ def test_wavefront_batch_equals_single_renders(wctx):
         for o, s1 in zip(outs, singles):
             np.testing.assert_array_equal(o.cpu().numpy(), s1.cpu().numpy())
     ctx.set_render_strategy("auto")
+
+
+@pytest.mark.parametrize("wd,ht,spp,stride", [(40, 40, 1, 1), (1280, 960, 2, 4)])
+def test_overlapped_rounds_equal_serial_rounds(wctx, wd, ht, spp, stride):
+    """The march kernel of round r+1 running beside the encoding and field kernels of round r
+    (two streams) gives exactly the image of the rounds run one after another."""
+    ctx = wctx["ctx"]
+    cam = sg.make_camera(wctx["w"].seed, 24, wd, ht)
+    cfg = _cfg(spp=spp, field_stride=stride, max_steps=1 << 20 if stride == 1 else 400,
+               t_min=0.0 if stride == 1 else 1e-3)
+    imgs = {}
+    for strategy in ("wavefront_serial", "wavefront"):
+        ctx.set_render_strategy(strategy)
+        for rep in range(2):
+            imgs[(strategy, rep)] = ctx.render_frame(cam, cfg).cpu().numpy()
+    ctx.set_render_strategy("auto")
+    ref = imgs[("wavefront_serial", 0)]
+    assert ref.mean() > 0
+    for k, v in imgs.items():
+        np.testing.assert_array_equal(v, ref, err_msg=str(k))
