@@ -374,55 +374,92 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
         ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
     }
     float gin = 0.0f;
-    float dir[8];
+    if (cnt > 0 && q == 0) gin = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
+    f3 S = {0.f, 0.f, 0.f};
+    if constexpr (P == P_F32) {
+      float dir[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dir[k] = 0.0f;
-    if (cnt > 0) {
-      if (q == 0) gin = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
+      for (int k = 0; k < 8; ++k) dir[k] = 0.0f;
+      if (cnt > 0) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int lv = 4 * q + k;
-        if (lv < F.levels) {
-          const float2 fd = load_feat2<P>(a.dfeat, (int64_t)lv * a.n_entries + t);
-          dir[2 * k] = fd.x;
-          dir[2 * k + 1] = fd.y;
+        for (int k = 0; k < 4; ++k) {
+          const int lv = 4 * q + k;
+          if (lv < F.levels) {
+            const float2 fd = load_feat2<P>(a.dfeat, (int64_t)lv * a.n_entries + t);
+            dir[2 * k] = fd.x;
+            dir[2 * k + 1] = fd.y;
+          }
         }
       }
-    }
-    f3 S = {0.f, 0.f, 0.f};
-    for (int k = 0; k < kmax; ++k) {
-      // an offset the compiler cannot see through: the weight reads stay inside the loop
-      // instead of being hoisted into (and spilling) registers
-      int wofs = 0;
-      asm volatile("" : "+s"(wofs));
-      const bool valid = k < cnt;
-      const int64_t sl = wf_slot(t, k);
-      float pos[8];
+      for (int k = 0; k < kmax; ++k) {
+        int wofs = 0;  // opaque offset: keeps the LDS weight reads inside the loop
+        asm volatile("" : "+s"(wofs));
+        const bool valid = k < cnt;
+        const int64_t sl = wf_slot(t, k);
+        float pos[8];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int lv = 4 * q + j;
-        float2 fp = make_float2(0.0f, 0.0f);
-        if (valid && lv < F.levels) fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + sl);
-        pos[2 * j] = fp.x;
-        pos[2 * j + 1] = fp.y;
+        for (int j = 0; j < 4; ++j) {
+          const int lv = 4 * q + j;
+          float2 fp = make_float2(0.0f, 0.0f);
+          if (valid && lv < F.levels) fp = load_feat2<P>(a.feat, (int64_t)lv * a.n_slots + sl);
+          pos[2 * j] = fp.x;
+          pos[2 * j + 1] = fp.y;
+        }
+        f3 W = {0.f, 0.f, 0.f};
+        if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
+        const f32x4 out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w) + wofs,
+                                            F.hidden, pos, dir, gin);
+        if (q == 0 && valid) {
+          S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+          S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+          S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+        }
       }
-      f3 W = {0.f, 0.f, 0.f};
-      if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
-      f32x4 out;
-      if constexpr (P == P_F32) {
-        out = mlp_forward16_f32(reinterpret_cast<const float *>(lds_w) + wofs, F.hidden, pos, dir,
-                                gin);
-      } else {
-        typedef Mma<P> M;
-        float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
-        out = mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w) + wofs, F.hidden,
-                               M::pack(pos), M::pack(dir), M::pack(gz));
+    } else {
+      // 16-bit features are stored as the matrix-core operand expects them (level 4q+j in
+      // 32-bit word j of lane group q), so loaded words become the B operand as they are
+      typedef Mma<P> M;
+      typedef typename M::vec vec;
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const uint32_t *fw = reinterpret_cast<const uint32_t *>(a.feat);
+      u32x4 dw = {0u, 0u, 0u, 0u};
+      if (cnt > 0) {
+        const uint32_t *dfw = reinterpret_cast<const uint32_t *>(a.dfeat);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (4 * q + k < F.levels) dw[k] = dfw[(int64_t)(4 * q + k) * a.n_entries + t];
       }
-      // lanes 0..15 hold the output of column `col`
-      if (q == 0 && valid) {
-        S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
-        S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
-        S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+      const vec b1 = __builtin_bit_cast(vec, dw);
+      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+      const vec b2 = M::pack(gz);
+      // the loads of query k+1 are issued before the network of query k runs
+      auto load_k = [&](int k, u32x4 &pw, f3 &W) {
+        pw = u32x4{0u, 0u, 0u, 0u};
+        W = {0.f, 0.f, 0.f};
+        if (k < cnt) {
+          const int64_t sl = wf_slot(t, k);
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (4 * q + j < F.levels) pw[j] = fw[(int64_t)(4 * q + j) * a.n_slots + sl];
+          if (q == 0) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
+        }
+      };
+      u32x4 pw;
+      f3 W;
+      load_k(0, pw, W);
+      for (int k = 0; k < kmax; ++k) {
+        int wofs = 0;  // opaque offset: keeps the LDS weight reads inside the loop
+        asm volatile("" : "+s"(wofs));
+        const u32x4 pc = pw;
+        const f3 Wc = W;
+        if (k + 1 < kmax) load_k(k + 1, pw, W);
+        const f32x4 out = mlp_forward16<P>(reinterpret_cast<const vec *>(lds_w) + wofs, F.hidden,
+                                           __builtin_bit_cast(vec, pc), b1, b2);
+        if (q == 0 && k < cnt) {
+          S.x = fmaf(Wc.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+          S.y = fmaf(Wc.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+          S.z = fmaf(Wc.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+        }
       }
     }
     // continuing rays carry the sum to the next round; ended rays (also those without a query
