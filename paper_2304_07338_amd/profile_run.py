@@ -3,7 +3,7 @@ field every 4 steps, FP16 matrix cores) a few times, plus one plain device copy 
 memory counters calibrate the HBM traffic counters.  The field keeps its initial parameters:
 the memory access pattern of a frame does not depend on the parameter values.
 
-    python -m paper_2304_07338_amd.profile_run [--frames 3]
+    python -m paper_2304_07338_amd.profile_run [--frames 3] [--strategy auto|fused|wavefront]
 """
 import argparse
 import os
@@ -18,6 +18,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=3)
     ap.add_argument("--precision", default="f16")
+    ap.add_argument("--strategy", default="auto",
+                    choices=["auto", "fused", "wavefront", "wavefront_serial"])
     args = ap.parse_args()
     import torch
     from paper_2304_07338_amd import scenegen as sg
@@ -27,6 +29,7 @@ def main():
     w = wl.C2
     vol, tf, lights = wl.make_scene(w, device="cuda:0")
     ctx = Context(0)
+    ctx.set_render_strategy(args.strategy)
     ctx.set_volume(vol.contiguous())
     ctx.set_transfer_function(tf, w.extinction)
     ctx.set_lights(sg.lights_array(lights))
