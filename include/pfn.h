@@ -242,12 +242,14 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  *     march loop and composites (the only form the persistent and graph launches use);
  *   PFN_STRATEGY_WAVEFRONT: rounds of a march kernel that stores up to 16 field queries per ray,
  *     level-major position-encoding kernels (each fine hashed level alone, so that its table
- *     stays in L2) and a matrix-core field kernel per 16-query ray tile; needs every job of the
- *     call to read one field slot and no graph capture, else the fused kernel runs;
+ *     stays in L2) and a matrix-core field kernel per 16-query ray tile; a batch runs one pass
+ *     of rounds per field slot it reads; never captured in graphs (the graph setting of
+ *     pfn_set_launch_mode applies to the fused kernel only);
  *     the march kernel of the next round runs on the context's stream while this round's
  *     encoding and field kernels run on a second stream the library owns (default priority);
  *   PFN_STRATEGY_WAVEFRONT_SERIAL: the same rounds, all on the context's stream;
- *   PFN_STRATEGY_AUTO (default): the wavefront form wherever it applies.
+ *   PFN_STRATEGY_AUTO (default): the wavefront form, unless graph replay was asked for (then
+ *     the fused kernel).
  * Device buffers of the wavefront form (two sets of about 1.5 KB per ray of a round, at most 2^21
  * rays per round, plus 24 B per ray sample of the frame) are kept in the context and grown on
  * demand.  Both wavefront variants give bit-identical images. */
@@ -258,11 +260,19 @@ typedef enum {
   PFN_STRATEGY_WAVEFRONT_SERIAL = 3
 } pfn_strategy;
 pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy);
-/* Autotuner: time every tile shape / block arrangement / launch mode on this batch (iters
- * launches each), keep the fastest for the context and return it (cached per batch shape). */
+/* Autotuner: time on this batch (iters launches each, after one warm-up launch) the render
+ * forms the strategy allows (PFN_STRATEGY_AUTO: the fused kernel and, for field-lit batches, the
+ * overlapped wavefront rounds; any other strategy: that form alone):
+ *   - the fused kernel in every tile shape / block arrangement / launch mode, replayed from
+ *     captured graphs if pfn_set_launch_mode asked for graphs;
+ *   - the wavefront rounds in every tile shape.
+ * It keeps the fastest for the context (tile shape, launch mode, and the render strategy, which
+ * becomes that form) and returns it.  Results are cached per batch shape and form (for the fused
+ * kernel, also per graph setting).  host_strategy receives the chosen pfn_strategy; host_ms the
+ * time of one launch of the batch in it; any output pointer may be NULL. */
 pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs,
                               int iters, int *host_tile_w, int *host_block_w, int *host_block_h,
-                              int *host_persistent, double *host_ms);
+                              int *host_persistent, int *host_strategy, double *host_ms);
 
 /* ------------------------------------------------------------------ timing */
 /* When enabled, the main kernels are bracketed by HIP events on the stream they run on; the

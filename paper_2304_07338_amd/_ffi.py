@@ -108,7 +108,8 @@ SIGNATURES = {
     "pfn_set_render_strategy": (C.c_int, [ctxp, C.c_int]),
     "pfn_autotune_batch": (C.c_int, [ctxp, C.POINTER(RenderJob), C.c_int, C.c_int,
                                      C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                                     C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_double)]),
     "pfn_timing_enable": (C.c_int, [ctxp, C.c_int]),
     "pfn_timing_get": (C.c_int, [ctxp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "pfn_timing_reset": (C.c_int, [ctxp]),

@@ -697,16 +697,29 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
     PFN_HIP(ctx, hipMemsetAsync(ctx->counters, 0, 16, ctx->stream));
     a.counters = ctx->counters;
   }
-  int wf_slot = -1;
-  if (p0.indirect == PFN_INDIRECT_FIELD && !ctx->use_graph && ctx->strategy != PFN_STRATEGY_FUSED) {
-    wf_slot = jobs[0].params.field_slot;
-    for (int i = 1; i < n_jobs; ++i)
-      if (jobs[i].params.field_slot != wf_slot) wf_slot = -1;
-  }
-  if (wf_slot >= 0) {
-    pfn_status st = run_wavefront(ctx, a, mj, p0.direct, prec, wf_slot, fd[wf_slot],
-                                  ctx->strategy != PFN_STRATEGY_WAVEFRONT_SERIAL);
-    if (st) return st;
+  // the wavefront form when the caller (or the autotuner) chose it, or by default where no
+  // graph replay was asked for; graph replay applies to the fused kernel only
+  const bool wavefront =
+      p0.indirect == PFN_INDIRECT_FIELD &&
+      (ctx->strategy == PFN_STRATEGY_WAVEFRONT || ctx->strategy == PFN_STRATEGY_WAVEFRONT_SERIAL ||
+       (ctx->strategy == PFN_STRATEGY_AUTO && !ctx->use_graph));
+  if (wavefront) {
+    // wavefront rounds, one pass per field slot in use (the field kernel stages one slot's
+    // weights); jobs keep their order within a pass
+    std::vector<int> slots;
+    for (int i = 0; i < n_jobs; ++i)
+      if (std::find(slots.begin(), slots.end(), jobs[i].params.field_slot) == slots.end())
+        slots.push_back(jobs[i].params.field_slot);
+    for (int s : slots) {
+      std::vector<MarchJob> part;
+      for (int i = 0; i < n_jobs; ++i)
+        if (jobs[i].params.field_slot == s) part.push_back(mj[i]);
+      MarchArgs ap = a;
+      ap.n_jobs = (int)part.size();
+      pfn_status st = run_wavefront(ctx, ap, part, p0.direct, prec, s, fd[s],
+                                    ctx->strategy != PFN_STRATEGY_WAVEFRONT_SERIAL);
+      if (st) return st;
+    }
   } else if (ctx->use_graph) {
     // replay a captured launch with the same arguments (the job table, field descriptors and
     // weight pointers it reads were refreshed above); capture it on first use
@@ -846,7 +859,8 @@ extern "C" pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_c
 // per (batch shape, modes, volume) in the context.
 extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs,
                                          int iters, int *out_tile_w, int *out_block_w,
-                                         int *out_block_h, int *out_persistent, double *out_ms) {
+                                         int *out_block_h, int *out_persistent, int *out_strategy,
+                                         double *out_ms) {
   CHECK_CTX(ctx);
   ARG(jobs && n_jobs >= 1 && n_jobs <= 4096, "1 to 4096 jobs");
   ARG(iters >= 1 && iters <= 100, "iters in [1, 100]");
@@ -864,11 +878,11 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
   pfn_status st = need_scene(ctx);
   if (st) return st;
   PFN_HIP(ctx, hipSetDevice(ctx->device));
-  // cache key: job sizes and modes, volume shape
-  std::vector<unsigned char> key;
-  auto put = [&key](const void *p, size_t n) {
+  // cache key: job sizes and modes, volume shape; the render form is appended per form
+  std::vector<unsigned char> base;
+  auto put = [&base](const void *p, size_t n) {
     const unsigned char *c = (const unsigned char *)p;
-    key.insert(key.end(), c, c + n);
+    base.insert(base.end(), c, c + n);
   };
   for (int i = 0; i < n_jobs; ++i) {
     put(&jobs[i].cam.width, sizeof(int));
@@ -880,51 +894,97 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
   put(&jobs[0].params.field_precision, sizeof(int));
   put(&ctx->vol_grid, sizeof(BrickGrid));
   put(&ctx->vol_dtype, sizeof(int));
+  // forms to time: the one the caller fixed, else the fused kernel and (field-lit batches) the
+  // overlapped wavefront rounds
+  const int saved_strategy = ctx->strategy;
+  std::vector<int> forms;
+  if (saved_strategy != PFN_STRATEGY_AUTO) forms.push_back(saved_strategy);
+  else {
+    forms.push_back(PFN_STRATEGY_FUSED);
+    if (jobs[0].params.indirect == PFN_INDIRECT_FIELD) forms.push_back(PFN_STRATEGY_WAVEFRONT);
+  }
+  if (jobs[0].params.indirect != PFN_INDIRECT_FIELD) forms.assign(1, PFN_STRATEGY_FUSED);
+  const bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;
   TileConfig best{};
   double best_ms = -1.0;
-  for (auto &e : ctx->tuned)
-    if (e.first == key) best = e.second, best_ms = 0.0;
-  if (best_ms < 0.0) {
-    hipEvent_t e0, e1;
-    PFN_HIP(ctx, hipEventCreate(&e0));
-    PFN_HIP(ctx, hipEventCreate(&e1));
-    const int tws[3] = {8, 16, 32};
-    const int arr[3][2] = {{2, 2}, {4, 1}, {1, 4}};
-    const int pers[3] = {0, 2, 4};
-    bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;
-    ctx->use_graph = false;
-    ctx->timing = false;
-    for (int tw : tws)
-      for (auto &ar : arr)
-        for (int pz : pers) {
-          TileConfig tc;
-          tc.tile_w = tw;
-          tc.tile_h = 64 / tw;
-          tc.block_w = ar[0];
-          tc.block_h = ar[1];
-          tc.persistent = pz;
-          st = run_march(ctx, jobs, n_jobs, tc);  // warm-up
-          if (st) break;
-          PFN_HIP(ctx, hipEventRecord(e0, ctx->stream));
-          for (int it = 0; it < iters && !st; ++it) st = run_march(ctx, jobs, n_jobs, tc);
-          PFN_HIP(ctx, hipEventRecord(e1, ctx->stream));
-          PFN_HIP(ctx, hipEventSynchronize(e1));
-          float ms = 0.0f;
-          PFN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-          double per = ms / iters;
-          if (best_ms < 0.0 || per < best_ms) {
-            best_ms = per;
-            best = tc;
-          }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  for (int form : forms) {
+    std::vector<unsigned char> key = base;
+    const int graph = form == PFN_STRATEGY_FUSED && saved_graph;
+    key.insert(key.end(), (const unsigned char *)&form, (const unsigned char *)&form + sizeof(int));
+    key.insert(key.end(), (const unsigned char *)&graph, (const unsigned char *)&graph + sizeof(int));
+    const TunedEntry *hit = nullptr;
+    for (const auto &e : ctx->tuned)
+      if (e.key == key) hit = &e;
+    TileConfig fbest{};
+    double fms = -1.0;
+    if (hit) {
+      fbest = hit->best;
+      fms = hit->ms;
+    } else {
+      if (!e0) {
+        PFN_HIP(ctx, hipEventCreate(&e0));
+        PFN_HIP(ctx, hipEventCreate(&e1));
+      }
+      // candidates: the fused kernel in every tile shape, block arrangement and launch mode;
+      // the wavefront rounds in every tile shape (the march kernel's ray tiles)
+      const int tws[3] = {8, 16, 32};
+      const int arr[3][2] = {{2, 2}, {4, 1}, {1, 4}};
+      const int pers[3] = {0, 2, 4};
+      std::vector<TileConfig> cands;
+      for (int tw : tws) {
+        TileConfig tc;
+        tc.tile_w = tw;
+        tc.tile_h = 64 / tw;
+        tc.strategy = form;
+        if (form != PFN_STRATEGY_FUSED) {
+          cands.push_back(tc);
+          continue;
         }
-    ctx->use_graph = saved_graph;
-    ctx->timing = saved_timing;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st) return st;
-    ctx->tuned.push_back({key, best});
+        for (auto &ar : arr)
+          for (int pz : pers) {
+            tc.block_w = ar[0];
+            tc.block_h = ar[1];
+            tc.persistent = pz;
+            cands.push_back(tc);
+          }
+      }
+      ctx->timing = false;
+      ctx->strategy = form;
+      ctx->use_graph = graph != 0;
+      for (const TileConfig &tc : cands) {
+        st = run_march(ctx, jobs, n_jobs, tc);  // warm-up (and graph capture)
+        if (st) break;
+        PFN_HIP(ctx, hipEventRecord(e0, ctx->stream));
+        for (int it = 0; it < iters && !st; ++it) st = run_march(ctx, jobs, n_jobs, tc);
+        PFN_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        PFN_HIP(ctx, hipEventSynchronize(e1));
+        if (st) break;
+        float ms = 0.0f;
+        PFN_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / iters;
+        if (fms < 0.0 || per < fms) {
+          fms = per;
+          fbest = tc;
+        }
+      }
+      ctx->use_graph = saved_graph;
+      ctx->timing = saved_timing;
+      ctx->strategy = saved_strategy;
+      if (st) break;
+      ctx->tuned.push_back({key, fbest, fms});
+    }
+    if (best_ms < 0.0 || fms < best_ms) {
+      best_ms = fms;
+      best = fbest;
+    }
   }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) return st;
   ctx->tile = best;
+  ctx->strategy = best.strategy;
+  if (out_strategy) *out_strategy = best.strategy;
   if (out_tile_w) *out_tile_w = best.tile_w;
   if (out_block_w) *out_block_w = best.block_w;
   if (out_block_h) *out_block_h = best.block_h;

@@ -37,6 +37,15 @@ struct FieldSlot {
 struct TileConfig {
   int tile_w = 8, tile_h = 8, block_w = 2, block_h = 2;
   int persistent = 0;  // 0: one workgroup per block; k: k persistent workgroups per CU
+  int strategy = 0;    // render form the autotuner chose (pfn_strategy)
+};
+
+// Autotuner result for one batch shape and render form (fused with or without graph replay,
+// wavefront, serial wavefront).
+struct TunedEntry {
+  std::vector<unsigned char> key;
+  TileConfig best;
+  double ms = 0.0;
 };
 
 // A captured ray-march launch, replayed while its launch arguments stay the same.
@@ -130,7 +139,7 @@ struct pfn_context {
   bool use_graph = false;
   hipStream_t cap_stream = nullptr;
   std::vector<MarchGraph> graphs;
-  std::vector<std::pair<std::vector<unsigned char>, TileConfig>> tuned;  // autotuner cache
+  std::vector<TunedEntry> tuned;  // autotuner cache, one entry per batch shape and render form
   int strategy = PFN_STRATEGY_AUTO;  // field renders: fused kernel or wavefront rounds
   WfState wf;
 

@@ -332,11 +332,14 @@ class Context:
 
     def autotune_batch(self, cams: List, cfgs: List[RenderConfig], outs=None, iters: int = 2):
         jobs, outs = self._jobs(cams, cfgs, outs)
-        tw, bw, bh, pz, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_double()
+        tw, bw, bh, pz, sg_ = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        ms = C.c_double()
         self._ok(self.lib.pfn_autotune_batch(self.h, jobs, len(cams), iters, C.byref(tw),
-                                             C.byref(bw), C.byref(bh), C.byref(pz), C.byref(ms)))
+                                             C.byref(bw), C.byref(bh), C.byref(pz), C.byref(sg_),
+                                             C.byref(ms)))
+        names = {v: k for k, v in STRATEGIES.items()}
         return dict(tile_w=tw.value, block_w=bw.value, block_h=bh.value, persistent=pz.value,
-                    ms=ms.value)
+                    strategy=names.get(sg_.value, sg_.value), ms=ms.value)
 
     def set_launch_mode(self, persistent_per_cu: int = 0, use_graph: bool = False):
         self._ok(self.lib.pfn_set_launch_mode(self.h, persistent_per_cu, int(use_graph)))

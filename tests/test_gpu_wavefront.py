@@ -150,3 +150,53 @@ def test_overlapped_rounds_equal_serial_rounds(wctx, wd, ht, spp, stride):
     assert ref.mean() > 0
     for k, v in imgs.items():
         np.testing.assert_array_equal(v, ref, err_msg=str(k))
+
+
+def test_wavefront_batch_with_two_field_slots(wctx):
+    """A batch whose jobs read two field slots runs one pass of rounds per slot and still
+    renders every job exactly as alone."""
+    import torch
+    from paper_2304_07338_amd.pfn import FieldConfig
+    ctx = wctx["ctx"]
+    ctx.field_select(1)
+    ctx.field_init(FieldConfig(log2_table=14), seed=5)
+    p = ctx.field_get_params()
+    g = torch.Generator(device="cuda:0").manual_seed(5)
+    ctx.field_set_params((p + 0.3 * torch.rand(p.shape, device="cuda:0", generator=g) - 0.15)
+                         .contiguous())
+    ctx.field_set_kappa(1e-2)
+    ctx.set_render_strategy("wavefront")
+    sizes = [(31, 17), (48, 40), (9, 64), (40, 33)]
+    cams = [sg.make_camera(wctx["w"].seed, 40 + i, wd, ht) for i, (wd, ht) in enumerate(sizes)]
+    cfgs = [_cfg(spp=1 + i % 2, field_slot=i % 2, seed=i) for i in range(len(sizes))]
+    singles = [ctx.render_frame(c, f).clone() for c, f in zip(cams, cfgs)]
+    outs = ctx.render_batch(cams, cfgs)
+    ctx.sync()
+    ctx.set_render_strategy("auto")
+    assert float(singles[0].mean()) != float(singles[1].mean())
+    for o, s1 in zip(outs, singles):
+        np.testing.assert_array_equal(o.cpu().numpy(), s1.cpu().numpy())
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_autotuner_chooses_among_forms_and_keeps_results_exact(wctx, use_graph):
+    """The autotuner times the fused kernel (graph-replayed when asked) and the wavefront rounds
+    and makes the faster the context's form; later renders use that form, whatever the graph
+    setting, and a batch still renders every job exactly as alone."""
+    ctx = wctx["ctx"]
+    ctx.set_render_strategy("auto")
+    ctx.set_launch_mode(0, use_graph)
+    sizes = [(64, 40), (33, 70), (80, 24)]
+    cams = [sg.make_camera(wctx["w"].seed, 50 + i, wd, ht) for i, (wd, ht) in enumerate(sizes)]
+    cfgs = [_cfg(spp=1, field_slot=0, seed=i) for i in range(len(sizes))]
+    best = ctx.autotune_batch(cams, cfgs, iters=1)
+    say("  autotuner choice", best)
+    assert best["strategy"] in ("fused", "wavefront")
+    singles = [ctx.render_frame(c, f).clone() for c, f in zip(cams, cfgs)]
+    outs = ctx.render_batch(cams, cfgs)
+    ctx.sync()
+    for o, s1 in zip(outs, singles):
+        np.testing.assert_array_equal(o.cpu().numpy(), s1.cpu().numpy())
+    ctx.set_render_strategy("auto")
+    ctx.set_tile_config(8, 2, 2)
+    ctx.set_launch_mode(0, False)
