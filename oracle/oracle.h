@@ -185,6 +185,35 @@ void orc_pt_pixels(const orc_scene *s, const orc_camera *c, int spp, int max_bou
                    int rr_start, uint64_t seed, int light_mask, int64_t n_pix, const int64_t *pix,
                    double *out);
 
+/* ---------------- First-interaction renderer (Section 3.6, Algorithm 2) ---------------- */
+/* One view ray per pixel through the pixel centre.  Each of its spp samples is an independent
+ * delta-tracking walk (global majorant) from the cube entry to the first real collision; a
+ * walk that leaves the cube is an invalid sample.  At a collision x with single-scattering
+ * albedo a(x): L_d = sum_l I_l p_g(mu_l) V_l / r_l^2 with V_l in {0, 1} from a delta-tracking
+ * walk toward light l, and L_i from the photon field (Eq. 2, decoded with Eq. 7) or the photon
+ * cache.  The sample contributes a(x) * (L_d + L_i); the pixel is the mean over its spp samples.
+ * Random numbers: the walk of sample s of pixel p uses Philox item p*spp + s of stream 10;
+ * the visibility walks of the k-th collision among samples 16j .. 16j+15 of pixel p use item
+ * p*spp + 16j + k of stream 11 (lights in order, one stream). */
+typedef struct {
+  int spp;
+  double g;
+  int indirect;     /* ORC_IND_NONE / ORC_IND_CACHE / ORC_IND_FIELD */
+  int light_mask;   /* bit l set -> light l contributes; 0 = all lights */
+  uint64_t seed;
+} orc_fi_params;
+
+/* Per sample, pixel-major ([n_pix][spp]): valid (1 = a collision), x[3], albedo[3], L_d[3] and
+ * L_i[3] (zero for invalid samples).  Any output may be NULL. */
+void orc_fi_samples(const orc_scene *s, const orc_camera *c, const orc_fi_params *p,
+                    const orc_cache *cache, const orc_field *field, int64_t n_pix,
+                    const int64_t *pix, int *valid, double *x, double *albedo, double *Ld,
+                    double *Li);
+/* Pixel values ([n_pix][3]). */
+void orc_fi_pixels(const orc_scene *s, const orc_camera *c, const orc_fi_params *p,
+                   const orc_cache *cache, const orc_field *field, int64_t n_pix,
+                   const int64_t *pix, double *out);
+
 /* ---------------- Metrics ---------------- */
 void orc_image_error(int64_t n, const double *img, const double *ref, double *rmse, double *rel_rmse,
                      double *psnr);

@@ -41,7 +41,9 @@ enum {
   ORC_STREAM_TRACE = 6,
   ORC_STREAM_TRAIN = 7,
   ORC_STREAM_RENDER = 8,
-  ORC_STREAM_PT = 9
+  ORC_STREAM_PT = 9,
+  ORC_STREAM_FI_SAMPLE = 10, /* first-interaction renderer: free-flight walks along view rays */
+  ORC_STREAM_FI_NEE = 11     /* first-interaction renderer: visibility walks toward the lights */
 };
 
 static inline double orc_dot(const double a[3], const double b[3]) {

@@ -19,6 +19,11 @@
  * Path tracer (the baseline of Section 4.3): delta tracking to real collisions, next-event
  * estimation with ratio tracking to every light, HG direction sampling, at most max_bounces
  * collisions, optional Russian roulette.
+ *
+ * First-interaction renderer (Section 3.6, Algorithm 2): ray generation, volume sampling by
+ * delta tracking (several first interactions along one view ray), the indirect light from the
+ * field at the interactions, direct light by next-event estimation with delta-tracking
+ * visibility, and composition.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -278,4 +283,123 @@ void orc_pt_pixels(const orc_scene *s, const orc_camera *cam, int spp, int max_b
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t i = 0; i < n_pix; ++i)
     pt_one(s, cam, spp, max_bounces, g, rr_start, seed, light_mask, majorant, pix[i], out + 3 * i);
+}
+
+/* ------------------------------------------------------------------ first-interaction renderer */
+/* Free-flight walk with the global majorant from x along unit d over [t, tmax): returns 1 and the
+ * collision distance at the first real collision, 0 if the walk passes tmax. */
+static int delta_track(const orc_scene *s, double majorant, const double x[3], const double d[3],
+                       double t, double tmax, orc_rng *rng, double *t_hit) {
+  if (!(majorant > 0.0)) return 0;
+  for (;;) {
+    t += -log(orc_rng_next(rng)) / majorant;
+    if (t >= tmax) return 0;
+    double xs[3] = {x[0] + t * d[0], x[1] + t * d[1], x[2] + t * d[2]};
+    double sig, alb[3];
+    orc_transfer(s, orc_density(s, xs), &sig, alb);
+    if (orc_rng_next(rng) < sig / majorant) {
+      *t_hit = t;
+      return 1;
+    }
+  }
+}
+
+static void fi_one(const orc_scene *s, const orc_camera *cam, const orc_fi_params *p,
+                   const orc_cache *cache, const orc_field *field, double majorant, int64_t pix,
+                   int *valid, double *xo, double *albo, double *Ldo, double *Lio) {
+  int ix = (int)(pix % cam->width), iy = (int)(pix / cam->width);
+  double o[3], d[3];
+  orc_camera_ray(cam, (double)ix + 0.5, (double)iy + 0.5, o, d);
+  double t0 = 0.0, t1 = 0.0;
+  const int hit = orc_clip_cube(o, d, &t0, &t1);
+  const double wo[3] = {-d[0], -d[1], -d[2]};
+  orc_render_params ip;
+  memset(&ip, 0, sizeof(ip));
+  ip.g = p->g;
+  ip.indirect = p->indirect;
+  int k = 0; /* collisions so far among the samples of the current group of 16 */
+  for (int smp = 0; smp < p->spp; ++smp) {
+    if (smp % 16 == 0) k = 0;
+    int ok = 0;
+    double x[3] = {0, 0, 0}, alb[3] = {0, 0, 0}, Ld[3] = {0, 0, 0}, Li[3] = {0, 0, 0};
+    if (hit) {
+      /* Volume sampling: the first real collision of this sample's walk */
+      orc_rng rng;
+      orc_rng_init(&rng, p->seed, (uint64_t)pix * (uint64_t)p->spp + (uint64_t)smp,
+                   ORC_STREAM_FI_SAMPLE);
+      double th;
+      ok = delta_track(s, majorant, o, d, t0, t1, &rng, &th);
+      if (ok) {
+        for (int c = 0; c < 3; ++c) x[c] = o[c] + th * d[c];
+        double sig;
+        orc_transfer(s, orc_density(s, x), &sig, alb);
+        /* Direct illumination: next-event estimation, visibility by delta tracking */
+        orc_rng vr;
+        orc_rng_init(&vr, p->seed,
+                     (uint64_t)pix * (uint64_t)p->spp + (uint64_t)(16 * (smp / 16) + k),
+                     ORC_STREAM_FI_NEE);
+        for (int l = 0; l < s->n_lights; ++l) {
+          if (!light_on(p->light_mask, l)) continue;
+          const double *L = s->lights + 6 * l;
+          double v[3] = {x[0] - L[0], x[1] - L[1], x[2] - L[2]};
+          double r2 = orc_dot(v, v);
+          double r = sqrt(r2);
+          double mu = orc_dot(v, wo) / r;
+          double dl[3] = {-v[0] / r, -v[1] / r, -v[2] / r};
+          double tmax = fmin(r, orc_exit_distance(x, dl));
+          double tb;
+          double V = delta_track(s, majorant, x, dl, 0.0, tmax, &vr, &tb) ? 0.0 : 1.0;
+          double w = orc_hg_eval(p->g, mu) * V / r2;
+          for (int c = 0; c < 3; ++c) Ld[c] += L[3 + c] * w;
+        }
+        /* Photon field prediction and decoding (or the cache) at the interaction */
+        indirect_light(&ip, cache, field, x, wo, Li);
+        ++k;
+      }
+    }
+    const int64_t j = (int64_t)smp;
+    if (valid) valid[j] = ok;
+    for (int c = 0; c < 3; ++c) {
+      if (xo) xo[3 * j + c] = x[c];
+      if (albo) albo[3 * j + c] = alb[c];
+      if (Ldo) Ldo[3 * j + c] = Ld[c];
+      if (Lio) Lio[3 * j + c] = Li[c];
+    }
+  }
+}
+
+void orc_fi_samples(const orc_scene *s, const orc_camera *cam, const orc_fi_params *p,
+                    const orc_cache *cache, const orc_field *field, int64_t n_pix,
+                    const int64_t *pix, int *valid, double *x, double *albedo, double *Ld,
+                    double *Li) {
+  const double majorant = orc_majorant(s);
+  const int64_t S = p->spp;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n_pix; ++i)
+    fi_one(s, cam, p, cache, field, majorant, pix[i], valid ? valid + i * S : NULL,
+           x ? x + 3 * i * S : NULL, albedo ? albedo + 3 * i * S : NULL,
+           Ld ? Ld + 3 * i * S : NULL, Li ? Li + 3 * i * S : NULL);
+}
+
+/* Composition: L = (1/spp) sum_k a_k (L_d,k + L_i,k); invalid samples contribute nothing. */
+void orc_fi_pixels(const orc_scene *s, const orc_camera *cam, const orc_fi_params *p,
+                   const orc_cache *cache, const orc_field *field, int64_t n_pix,
+                   const int64_t *pix, double *out) {
+  const int64_t S = p->spp;
+  double *alb = (double *)malloc(sizeof(double) * 3 * S * (size_t)(n_pix > 0 ? n_pix : 1));
+  double *Ld = (double *)malloc(sizeof(double) * 3 * S * (size_t)(n_pix > 0 ? n_pix : 1));
+  double *Li = (double *)malloc(sizeof(double) * 3 * S * (size_t)(n_pix > 0 ? n_pix : 1));
+  orc_fi_samples(s, cam, p, cache, field, n_pix, pix, NULL, NULL, alb, Ld, Li);
+  for (int64_t i = 0; i < n_pix; ++i)
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      for (int64_t j = 0; j < S; ++j) {
+        const size_t q = (size_t)(3 * (i * S + j) + c);
+        acc += alb[q] * (Ld[q] + Li[q]);
+      }
+      out[3 * i + c] = acc / (double)S;
+    }
+  free(alb);
+  free(Ld);
+  free(Li);
 }

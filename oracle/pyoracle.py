@@ -79,6 +79,11 @@ class RenderParams(C.Structure):
                 ("lv_step_voxels", C.c_double), ("seed", C.c_uint64)]
 
 
+class FiParams(C.Structure):
+    _fields_ = [("spp", C.c_int), ("g", C.c_double), ("indirect", C.c_int),
+                ("light_mask", C.c_int), ("seed", C.c_uint64)]
+
+
 class Field(C.Structure):
     _fields_ = [("desc", C.POINTER(FieldDesc)), ("params", dp), ("rounding", C.c_int),
                 ("kappa", C.c_double)]
@@ -154,6 +159,11 @@ def lib():
         L.orc_lightvol_res.argtypes = [C.c_int]
         L.orc_pt_pixels.argtypes = [C.POINTER(Scene), C.POINTER(CameraS), C.c_int, C.c_int,
                                     C.c_double, C.c_int, C.c_uint64, C.c_int, C.c_int64, i64p, dp]
+        L.orc_fi_samples.argtypes = [C.POINTER(Scene), C.POINTER(CameraS), C.POINTER(FiParams),
+                                     C.POINTER(Cache), C.POINTER(Field), C.c_int64, i64p,
+                                     C.POINTER(C.c_int), dp, dp, dp, dp]
+        L.orc_fi_pixels.argtypes = [C.POINTER(Scene), C.POINTER(CameraS), C.POINTER(FiParams),
+                                    C.POINTER(Cache), C.POINTER(Field), C.c_int64, i64p, dp]
         L.orc_image_error.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -461,6 +471,60 @@ def pt_pixels(scene: OracleScene, cam, spp, max_bounces=8, g=0.0, rr_start=0, se
     out = np.zeros((pixels.size, 3))
     lib().orc_pt_pixels(scene.ref, C.byref(cs), spp, max_bounces, g, rr_start, seed, light_mask,
                         pixels.size, _ptr(pixels, i64p), _ptr(out))
+    return out
+
+
+def _fi_refs(params, cache, field):
+    if params.indirect == IND_CACHE and cache is None:
+        raise ValueError("indirect = cache needs a cache")
+    if params.indirect == IND_FIELD and field is None:
+        raise ValueError("indirect = field needs a field")
+    cref = cache.ref if cache is not None else None
+    if field is None:
+        return cref, None, None
+    desc, fp, rounding, kappa = field
+    keep = _d(fp)
+    fs = Field(C.pointer(desc), _ptr(keep), rounding, kappa)
+    return cref, fs, keep
+
+
+def fi_params(spp=1, g=0.0, indirect=IND_NONE, light_mask=0, seed=0) -> FiParams:
+    return FiParams(spp, g, indirect, light_mask, seed)
+
+
+def fi_samples(scene: OracleScene, cam, params: FiParams, pixels=None,
+               cache: Optional[OracleCache] = None, field=None):
+    """First-interaction renderer, per sample: dict of valid [n, spp], x, albedo, Ld, Li
+    [n, spp, 3].  field = (desc, params_array, rounding, kappa) or None."""
+    if pixels is None:
+        pixels = np.arange(cam.width * cam.height, dtype=np.int64)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    n, S = pixels.size, params.spp
+    cs = camera_struct(cam)
+    valid = np.zeros((n, S), dtype=np.int32)
+    out = {k: np.zeros((n, S, 3)) for k in ("x", "albedo", "Ld", "Li")}
+    cref, fs, keep = _fi_refs(params, cache, field)
+    lib().orc_fi_samples(scene.ref, C.byref(cs), C.byref(params), cref,
+                         C.byref(fs) if fs is not None else None, n, _ptr(pixels, i64p),
+                         valid.ctypes.data_as(C.POINTER(C.c_int)), _ptr(out["x"]),
+                         _ptr(out["albedo"]), _ptr(out["Ld"]), _ptr(out["Li"]))
+    del keep
+    out["valid"] = valid
+    return out
+
+
+def fi_pixels(scene: OracleScene, cam, params: FiParams, pixels=None,
+              cache: Optional[OracleCache] = None, field=None) -> np.ndarray:
+    if pixels is None:
+        pixels = np.arange(cam.width * cam.height, dtype=np.int64)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    cs = camera_struct(cam)
+    out = np.zeros((pixels.size, 3))
+    cref, fs, keep = _fi_refs(params, cache, field)
+    lib().orc_fi_pixels(scene.ref, C.byref(cs), C.byref(params), cref,
+                        C.byref(fs) if fs is not None else None, pixels.size,
+                        _ptr(pixels, i64p), _ptr(out))
+    del keep
     return out
 
 
