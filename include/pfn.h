@@ -217,6 +217,24 @@ typedef struct {
  * g and field slot).  All jobs must share indirect/direct mode and field precision. */
 pfn_status pfn_render_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs);
 
+/* First-interaction renderer (Section 3.6, Algorithm 2).  One view ray per pixel through the
+ * pixel centre; each of its spp samples is an independent delta-tracking walk (global majorant of
+ * sigma_t) from the cube entry to the first real collision, and a walk that leaves the cube is an
+ * invalid sample.  The collisions are compacted and the indirect light at all of them comes from
+ * one batched pass of the field (or the photon cache, or none); the direct light is next-event
+ * estimation toward every selected light with a delta-tracking visibility walk (V in {0, 1}).
+ * Pixel = (1/spp) sum over valid samples of albedo * (L_d + L_i): a collision sampled in
+ * proportion to sigma_t scatters with probability albedo = sigma_s / sigma_t, and the MIS
+ * weights are 1 because point lights cannot be reached by phase sampling.
+ * Uses spp, g, indirect, field_precision, light_mask, field_slot and seed of p (the march fields
+ * and `direct` are ignored).  Random numbers: Philox item pixel * spp + s of stream 10 for the
+ * walk of sample s; item pixel * spp + 16 j + k of stream 11 for the visibility walks of the k-th
+ * collision among samples 16 j .. 16 j + 15.  Output dev_rgb_out: height x width x 3 floats.
+ * Device buffers are those of the wavefront ray marcher (kept in the context); the direct-light
+ * kernel runs on the library's second stream beside the field pass. */
+pfn_status pfn_render_first_interaction(pfn_context *ctx, const pfn_camera *cam,
+                                        const pfn_render_params *p, float *dev_rgb_out);
+
 /* Monte Carlo volumetric path tracer (the baseline of Section 4.3): delta tracking, next-event
  * estimation with ratio tracking, HG sampling, at most max_bounces collisions. */
 pfn_status pfn_render_path_traced(pfn_context *ctx, const pfn_camera *cam, int spp,
@@ -280,7 +298,10 @@ pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs,
  * kernel: 0 = ray march (a whole frame or batch, every kernel of it), 1 = photon trace,
  * 2 = training step (fused forward/backward), 3 = path tracer, 4 = field query, 5 = Adam;
  * kernels of the wavefront render: 6 = march rounds, 7 = position-encoding launches,
- * 8 = matrix-core field tiles, 9 = pixel resolve.  Ids 0..15 are valid. */
+ * 8 = matrix-core field tiles, 9 = pixel resolve (the first-interaction renderer also reports
+ * its field pass under 7 and 8 and its resolve under 9); first-interaction renderer:
+ * 10 = ray generation, delta-tracking sampling and compaction, 11 = next-event estimation.
+ * Ids 0..15 are valid. */
 pfn_status pfn_timing_enable(pfn_context *ctx, int on);
 pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);
 pfn_status pfn_timing_reset(pfn_context *ctx);

@@ -16,6 +16,7 @@ INDIRECT_NONE, INDIRECT_CACHE, INDIRECT_FIELD = 0, 1, 2
 DIRECT_SHADOW_RAYS, DIRECT_LIGHT_VOLUME = 0, 1
 TK_MARCH, TK_TRACE, TK_TRAIN, TK_PT, TK_QUERY, TK_ADAM = 0, 1, 2, 3, 4, 5
 TK_WF_MARCH, TK_WF_ENCODE, TK_WF_FIELD, TK_WF_RESOLVE = 6, 7, 8, 9
+TK_FI_SAMPLE, TK_FI_NEE = 10, 11
 
 
 class PointLight(C.Structure):
@@ -98,6 +99,8 @@ SIGNATURES = {
     "pfn_field_adam_step": (C.c_int, [ctxp, vp, C.c_int64, C.c_float, C.c_float, C.c_float,
                                       C.c_float]),
     "pfn_render_frame": (C.c_int, [ctxp, C.POINTER(CameraS), C.POINTER(RenderParams), vp]),
+    "pfn_render_first_interaction": (C.c_int, [ctxp, C.POINTER(CameraS), C.POINTER(RenderParams),
+                                               vp]),
     "pfn_render_batch": (C.c_int, [ctxp, C.POINTER(RenderJob), C.c_int]),
     "pfn_render_path_traced": (C.c_int, [ctxp, C.POINTER(CameraS), C.c_int, C.c_int, C.c_float,
                                          C.c_int, C.c_int, C.c_uint64, vp]),

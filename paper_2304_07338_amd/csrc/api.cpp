@@ -609,7 +609,8 @@ static void fill_job(pfn_context *ctx, const pfn_camera *c, const pfn_render_par
   j.ray_begin = 0;
 }
 
-pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc) {
+pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc,
+                     bool first_interaction) {
   const pfn_render_params &p0 = jobs[0].params;
   std::vector<MarchJob> mj(n_jobs);
   int total = 0;
@@ -703,7 +704,11 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
       p0.indirect == PFN_INDIRECT_FIELD &&
       (ctx->strategy == PFN_STRATEGY_WAVEFRONT || ctx->strategy == PFN_STRATEGY_WAVEFRONT_SERIAL ||
        (ctx->strategy == PFN_STRATEGY_AUTO && !ctx->use_graph));
-  if (wavefront) {
+  if (first_interaction) {
+    pfn_status st = run_first_interaction(ctx, a, mj[0], p0.indirect, prec, p0.field_slot,
+                                          fd[p0.field_slot]);
+    if (st) return st;
+  } else if (wavefront) {
     // wavefront rounds, one pass per field slot in use (the field kernel stages one slot's
     // weights); jobs keep their order within a pass
     std::vector<int> slots;
@@ -778,6 +783,25 @@ extern "C" pfn_status pfn_render_frame(pfn_context *ctx, const pfn_camera *cam,
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   pfn_render_job job{*cam, *p, dev_rgb_out};
   return run_march(ctx, &job, 1, ctx->tile);
+}
+
+extern "C" pfn_status pfn_render_first_interaction(pfn_context *ctx, const pfn_camera *cam,
+                                                   const pfn_render_params *p,
+                                                   float *dev_rgb_out) {
+  CHECK_CTX(ctx);
+  pfn_status st = check_camera(ctx, cam);
+  if (st) return st;
+  ARG(p, "render params are NULL");
+  pfn_render_params q = *p;
+  q.direct = PFN_DIRECT_SHADOW_RAYS;  // direct light comes from delta-tracking visibility
+  st = check_render_params(ctx, &q);
+  if (st) return st;
+  ARG(dev_rgb_out, "output is NULL");
+  st = need_scene(ctx);
+  if (st) return st;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  pfn_render_job job{*cam, q, dev_rgb_out};
+  return run_march(ctx, &job, 1, ctx->tile, true);
 }
 
 extern "C" pfn_status pfn_render_batch(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs) {

@@ -168,7 +168,8 @@ struct pfn_context {
 
 enum TimedKernel {
   TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5,
-  TK_WF_MARCH = 6, TK_WF_ENCODE = 7, TK_WF_FIELD = 8, TK_WF_RESOLVE = 9
+  TK_WF_MARCH = 6, TK_WF_ENCODE = 7, TK_WF_FIELD = 8, TK_WF_RESOLVE = 9, TK_FI_SAMPLE = 10,
+  TK_FI_NEE = 11
 };
 
 // Error helpers
@@ -203,7 +204,11 @@ FieldDev make_field_dev(const FieldSlot &f, int prec);
 pfn_status field_refresh(pfn_context *ctx, FieldSlot &f, int prec);
 void field_params_changed(FieldSlot &f);
 pfn_status alloc_cache(pfn_context *ctx, int n_bins, int res);
-pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc);
+pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc,
+                     bool first_interaction = false);
+// First-interaction renderer (one job): sampling, direct light, field pass and resolve.
+pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob job, int indirect,
+                                 int prec, int slot, const FieldDev &fd_host);
 hipError_t launch_cache_pack(pfn_context *ctx, const float *src, size_t cells);
 hipError_t launch_cache_unpack(pfn_context *ctx, float *dst, size_t cells);
 pfn_status count_records(pfn_context *ctx, uint64_t *out);

@@ -60,7 +60,14 @@ struct Philox {
   }
 };
 
-enum : uint32_t { STREAM_TRACE = 6, STREAM_TRAIN = 7, STREAM_RENDER = 8, STREAM_PT = 9 };
+enum : uint32_t {
+  STREAM_TRACE = 6,
+  STREAM_TRAIN = 7,
+  STREAM_RENDER = 8,
+  STREAM_PT = 9,
+  STREAM_FI_SAMPLE = 10,  // first-interaction renderer: free-flight walks along view rays
+  STREAM_FI_NEE = 11      // first-interaction renderer: visibility walks toward the lights
+};
 
 // ------------------------------------------------------------------ small vector math
 struct f3 {

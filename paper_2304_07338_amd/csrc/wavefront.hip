@@ -22,29 +22,8 @@
 // is the fused kernel's; only the order in which the FP32 terms are added differs.  Results do
 // not depend on the lane or list position a ray gets, so a frame is deterministic and a batch
 // renders exactly as its jobs rendered alone.
-#include "march.h"
-#include "march_dev.h"
-#include "pfn_ctx.h"
+#include "wavefront.h"
 
-#define WF_THREADS 256
-#define WF_SLOTS 16                  // queries per ray per round: one matrix-core tile
-#define WF_MAX_ENTRIES (1 << 21)     // rays per round
-#define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
-#ifndef WF_GROUP_BYTES
-#define WF_GROUP_BYTES (64u << 20)   // table bytes the coarse levels of one encoding launch span
-#endif
-
-// Query slot k of round entry t.  Slots are tiled as [t / 64][k][t % 64]: the 64 rays of a march
-// wave write slot k of 64 consecutive entries, and 16 neighbouring rays' slot k are 64
-// contiguous bytes for the field kernel.
-__host__ __device__ __forceinline__ int64_t wf_slot(int64_t t, int k) {
-  return ((t >> 6) << 10) | ((int64_t)k << 6) | (t & 63);
-}
-// Slots spanned by the first n entries.
-__host__ __device__ __forceinline__ int64_t wf_slots(int64_t n) { return ((n + 63) >> 6) << 10; }
-
-// Rays continued from the previous round: ray id, next step, transmittance and the direct and
-// indirect sums so far (RGB, entry-major).
 struct WfList {
   uint32_t *ray;
   int *j;
@@ -68,61 +47,6 @@ struct WfArgs {
   float *qx, *qy, *qz, *wr, *wg, *wb;
   float *acc_d, *acc_i;  // per ray sample: final direct and indirect RGB sums
 };
-
-struct WfEncArgs {
-  const FieldDev *F;
-  const int *ent_cnt;
-  const float *qx, *qy, *qz;
-  void *feat;           // [level][slot]: uint32 (two 16-bit features) or float2 (FP32)
-  int64_t n_slots;
-  int n_entries;
-  int l0, l1;
-};
-
-struct WfDirArgs {
-  const FieldDev *F;
-  const int *ent_cnt;
-  const float2 *ent_u;
-  void *dfeat;          // [level][entry]
-  int n_entries;
-};
-
-struct WfFieldArgs {
-  const FieldDev *F;
-  const void *mlp;
-  int mlp_bytes;
-  const MarchJob *jobs;
-  int n_jobs;
-  const uint32_t *ent_ray;
-  const int *ent_cnt;
-  const int *ent_next;
-  const float *wr, *wg, *wb;
-  const void *feat, *dfeat;
-  const float *in_ci;   // carried indirect sums of the continued entries [0, n_cont)
-  float *out_ci;
-  float *acc_i;
-  int64_t n_slots;
-  int n_entries, n_cont;
-};
-
-struct WfResolveArgs {
-  const MarchJob *jobs;
-  int n_jobs;
-  const int64_t *pix_begin;  // per job, plus the total at [n_jobs]
-  const float *acc_d, *acc_i;
-  int tile_w, tile_h;
-};
-
-// Job of ray r: the last job whose first ray is <= r.
-__device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, int64_t r) {
-  int lo = 0, hi = n_jobs - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].ray_begin <= r) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 // One ray of the round (see wf_march_kernel); `job` is uniform across the calling lanes.
 template <typename VT, int DIRECT>
@@ -318,14 +242,24 @@ __device__ __forceinline__ float2 load_feat2(const void *feat, int64_t i) {
 
 template <int P>
 __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
-  const int64_t s = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
-  if (s >= e.n_slots) return;
-  const int64_t t = ((s >> 10) << 6) | (s & 63);
-  const int c = (int)((s >> 6) & 15);
+  // thread g: query c of entry t, over the first 2^kshift query indices of every entry (and,
+  // with per_level, one level of it)
+  int64_t g = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
+  int l0 = e.l0, l1 = e.l1;
+  if (e.per_level) {
+    const int dl = (int)(g / e.per_level);
+    g -= (int64_t)dl * e.per_level;
+    l0 += dl;
+    l1 = l0 + 1;
+    if (l0 >= e.l1) return;
+  }
+  const int64_t t = ((g >> (6 + e.kshift)) << 6) | (g & 63);
+  const int c = (int)((g >> 6) & ((1 << e.kshift) - 1));
   if (t >= e.n_entries || c >= e.ent_cnt[t]) return;
+  const int64_t s = wf_slot(t, c);
   const FieldDev &F = *e.F;
   const f3 x = clamp01(f3{e.qx[s], e.qy[s], e.qz[s]});
-  for (int lv = e.l0; lv < e.l1; ++lv)
+  for (int lv = l0; lv < l1; ++lv)
     store_feat<P>(e.feat, (int64_t)lv * e.n_slots + s, encode_pos_level<P>(F, lv, x));
 }
 
@@ -532,9 +466,7 @@ static void free_entries(WfState &w) {
   w.feat_elem = 0;
 }
 
-// Buffers for `entries` rays per round, `rays` ray samples per frame and feature elements of
-// `feat_bytes` bytes; kept between frames and grown on demand.
-static hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes) {
+hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes) {
   hipError_t e = hipSuccess;
   if (entries > w.ent_cap || feat_bytes > w.feat_elem) {
     free_entries(w);
@@ -611,12 +543,15 @@ static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
 template <int P>
 static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, const WfDirArgs &dg,
                        const std::vector<std::pair<int, int>> &groups, const WfFieldArgs &f,
-                       int field_blocks) {
-  const int eb = (int)((e.n_slots + WF_THREADS - 1) / WF_THREADS);
+                       int field_blocks, bool split_levels) {
+  const int64_t threads = (((int64_t)e.n_entries + 63) >> 6) << (6 + e.kshift);
   for (auto &g : groups) {
     WfEncArgs ee = e;
     ee.l0 = g.first;
     ee.l1 = g.second;
+    ee.per_level = split_levels && g.second - g.first > 1 ? (int)threads : 0;
+    const int64_t n = ee.per_level ? threads * (g.second - g.first) : threads;
+    const int eb = (int)((n + WF_THREADS - 1) / WF_THREADS);
     const int ts = timing_begin_on(ctx, st);
     hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
     timing_end_on(ctx, ts, TK_WF_ENCODE, st);
@@ -633,6 +568,14 @@ static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, con
   timing_end_on(ctx, ts, TK_WF_FIELD, st);
 }
 
+void wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
+                          const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
+                          const WfFieldArgs &f, int field_blocks, bool split_levels) {
+  if (prec == P_F32) launch_k23<P_F32>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
+  else if (prec == P_BF16) launch_k23<P_BF16>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
+  else launch_k23<P_F16>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
+}
+
 template <int P>
 static int field_blocks_resident(int mlp_bytes) {
   int per_cu = 0;
@@ -645,6 +588,44 @@ static int field_blocks_resident(int mlp_bytes) {
   if (hipGetDevice(&dev) == hipSuccess)
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   return per_cu * cus;
+}
+
+int wf_field_blocks(int prec, int mlp_bytes) {
+  return prec == P_F32    ? field_blocks_resident<P_F32>(mlp_bytes)
+         : prec == P_BF16 ? field_blocks_resident<P_BF16>(mlp_bytes)
+                          : field_blocks_resident<P_F16>(mlp_bytes);
+}
+
+std::vector<std::pair<int, int>> wf_level_groups(const pfn_context *ctx, int slot,
+                                                 const FieldDev &fd_host, size_t fbytes) {
+  std::vector<std::pair<int, int>> groups;
+  const FieldSlot &fs = ctx->fields[slot];
+  const int L = fd_host.levels;
+  auto fine = [&](int l) {
+    return !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
+  };
+  auto bytes = [&](int l) {
+    const size_t end = l + 1 < L ? fd_host.pos.off[l + 1] : fs.pos_entries;
+    return (end - fd_host.pos.off[l]) * fbytes;
+  };
+  int l = 0;
+  while (l < L) {
+    int e = l + 1;
+    if (!fine(l)) {
+      size_t b = bytes(l);
+      while (e < L && !fine(e) && b + bytes(e) <= WF_GROUP_BYTES) b += bytes(e++);
+    }
+    groups.push_back({l, e});
+    l = e;
+  }
+  return groups;
+}
+
+void wf_launch_resolve(pfn_context *ctx, hipStream_t st, const WfResolveArgs &ra, int64_t pixels) {
+  const int ts = timing_begin_on(ctx, st);
+  hipLaunchKernelGGL(wf_resolve_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0, st,
+                     ra);
+  timing_end_on(ctx, ts, TK_WF_RESOLVE, st);
 }
 
 // Rounds of the wavefront render.  The march kernel of round r runs on the context's stream;
@@ -682,33 +663,8 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
                               hipMemcpyHostToDevice, ctx->stream));
   PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
 
-  // level groups of the position encoding: the coarse levels together, each fine hashed
-  // level alone
-  std::vector<std::pair<int, int>> groups;
-  {
-    const FieldSlot &fs = ctx->fields[slot];
-    const int L = fd_host.levels;
-    auto fine = [&](int l) {
-      return !((fd_host.pos.dense_mask >> l) & 1u) && fd_host.pos.res[l] >= WF_FINE_RES;
-    };
-    auto bytes = [&](int l) {
-      const size_t end = l + 1 < L ? fd_host.pos.off[l + 1] : fs.pos_entries;
-      return (end - fd_host.pos.off[l]) * fbytes;
-    };
-    int l = 0;
-    while (l < L) {
-      int e = l + 1;
-      if (!fine(l)) {
-        size_t b = bytes(l);
-        while (e < L && !fine(e) && b + bytes(e) <= WF_GROUP_BYTES) b += bytes(e++);
-      }
-      groups.push_back({l, e});
-      l = e;
-    }
-  }
-  const int fb_max = prec == P_F32   ? field_blocks_resident<P_F32>(m.mlp_bytes)
-                     : prec == P_BF16 ? field_blocks_resident<P_BF16>(m.mlp_bytes)
-                                      : field_blocks_resident<P_F16>(m.mlp_bytes);
+  const std::vector<std::pair<int, int>> groups = wf_level_groups(ctx, slot, fd_host, fbytes);
+  const int fb_max = wf_field_blocks(prec, m.mlp_bytes);
   hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream;
 
   const int tslot = timing_begin(ctx);
@@ -770,6 +726,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     e.feat = b.feat;
     e.n_slots = wf_slots(n_in);
     e.n_entries = n_in;
+    e.kshift = 4;
     WfDirArgs dg{};
     dg.F = m.fields + slot;
     dg.ent_cnt = b.ent_cnt;
@@ -798,9 +755,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     f.out_ci = w.list_ci[cur ^ 1];
     const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));
     if (overlap) PFN_HIP(ctx, hipStreamWaitEvent(sb, w.ev_march[p], 0));
-    if (prec == P_F32) launch_k23<P_F32>(ctx, sb, e, dg, groups, f, fb);
-    else if (prec == P_BF16) launch_k23<P_BF16>(ctx, sb, e, dg, groups, f, fb);
-    else launch_k23<P_F16>(ctx, sb, e, dg, groups, f, fb);
+    wf_launch_field_pass(ctx, sb, prec, e, dg, groups, f, fb);
     PFN_HIP(ctx, hipGetLastError());
     PFN_HIP(ctx, hipEventRecord(w.ev_field[p], sb));
 
@@ -823,10 +778,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   ra.acc_i = w.acc_i;
   ra.tile_w = m.tile_w;
   ra.tile_h = m.tile_h;
-  const int tsr = timing_begin(ctx);
-  hipLaunchKernelGGL(wf_resolve_kernel, dim3((unsigned)((pixels + 255) / 256)), dim3(256), 0, sa,
-                     ra);
-  timing_end(ctx, tsr, TK_WF_RESOLVE);
+  wf_launch_resolve(ctx, sa, ra, pixels);
   PFN_HIP(ctx, hipGetLastError());
   timing_end(ctx, tslot, TK_MARCH);
   return PFN_OK;

@@ -312,6 +312,21 @@ class Context:
         self._ok(self.lib.pfn_render_frame(self.h, C.byref(c), C.byref(p), _ptr(out)))
         return out
 
+    def render_first_interaction(self, cam, cfg: RenderConfig, out=None):
+        """Algorithm 2 of the paper: delta-tracked first interactions along the pixel-centre
+        ray (cfg.spp per pixel), one batched field (or cache) pass over the compacted
+        interactions, next-event estimation with delta-tracking visibility, albedo-weighted
+        composition.  Uses spp, g, indirect, field_precision, light_mask, field_slot, seed."""
+        import torch
+        if out is None:
+            out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32,
+                              device=f"cuda:{self.device}")
+        _check(out, torch.float32, cam.width * cam.height * 3, "out")
+        c = camera_struct(cam)
+        p = cfg.struct()
+        self._ok(self.lib.pfn_render_first_interaction(self.h, C.byref(c), C.byref(p), _ptr(out)))
+        return out
+
     def _jobs(self, cams, cfgs, outs):
         import torch
         n = len(cams)
