@@ -1,9 +1,12 @@
 """Profiling driver: renders the 1080p photon-field frame of the benchmark (512^3 f16 volume,
 field every 4 steps, FP16 matrix cores) a few times, plus one plain device copy of 1 GiB whose
 memory counters calibrate the HBM traffic counters.  The field keeps its initial parameters:
-the memory access pattern of a frame does not depend on the parameter values.
+the memory access pattern of a ray-marched frame does not depend on the parameter values.
+With --renderer first_interaction it renders the same view with the Algorithm 2 renderer at 1
+spp instead (at --width x --height).
 
     python -m paper_2304_07338_amd.profile_run [--frames 3] [--strategy auto|fused|wavefront]
+        [--renderer march|first_interaction] [--width 1920 --height 1080]
 """
 import argparse
 import os
@@ -20,6 +23,9 @@ def main():
     ap.add_argument("--precision", default="f16")
     ap.add_argument("--strategy", default="auto",
                     choices=["auto", "fused", "wavefront", "wavefront_serial"])
+    ap.add_argument("--renderer", default="march", choices=["march", "first_interaction"])
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
     args = ap.parse_args()
     import torch
     from paper_2304_07338_amd import scenegen as sg
@@ -36,13 +42,16 @@ def main():
     ctx.build_light_volume(0.5)
     ctx.trace_photon_cache(1 << 22, wl.C1_G_BINS, cache_res=128, seed=6)
     ctx.field_init(FieldConfig(), seed=1)
-    cam = wl.camera(w, 0)
+    cam0 = wl.camera(w, 0)
+    cam = sg.Camera(cam0.eye, cam0.target, cam0.up, cam0.fov_y_deg, args.width, args.height)
     rc = RenderConfig(spp=1, step_voxels=0.5, max_steps=1024, t_min=1e-3, field_stride=4, g=0.4,
                       indirect=INDIRECT_FIELD, direct=DIRECT_LIGHT_VOLUME,
                       field_precision=args.precision)
-    out = torch.empty((w.height, w.width, 3), dtype=torch.float32, device="cuda:0")
+    out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device="cuda:0")
+    render = ctx.render_first_interaction if args.renderer == "first_interaction" else \
+        ctx.render_frame
     for i in range(args.frames):
-        ctx.render_frame(cam, rc, out)
+        render(cam, rc, out)
         torch.cuda.synchronize()
         print(f"frame {i} done", flush=True)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
