@@ -8,7 +8,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle_core.c", "oracle_field.c", "oracle_trace.c", "oracle_render.c"]
+SOURCES = ["oracle_core.c", "oracle_field.c", "oracle_trace.c", "oracle_render.c",
+           "oracle_photonmap.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -214,6 +214,20 @@ void orc_fi_pixels(const orc_scene *s, const orc_camera *c, const orc_fi_params 
                    const orc_cache *cache, const orc_field *field, int64_t n_pix,
                    const int64_t *pix, double *out);
 
+/* ---------------- Photon-map radiance estimate (Eq. 5, Section 3.3) ---------------- */
+/* Collision-estimator score Phi / sigma_t(x) of n records ([n][3] each). */
+void orc_pm_scores(const orc_scene *s, int64_t n, const double *x, const double *power,
+                   double *score);
+/* Eq. (5) at n_q queries (position [3], unit direction of the scattered light [3], bin) over
+ * n_rec records (position, incident direction, score, bin), brute force.  k = 0: every record of
+ * the bin within `radius`, divided by the volume of that sphere; k > 0: the k nearest within
+ * `radius`, divided by the sphere through the farthest of them.  out [n_q][3]; r_used and n_used
+ * (may be NULL) receive the radius and the record count of each estimate. */
+void orc_pm_estimate(int64_t n_rec, const double *rx, const double *rw, const double *rs,
+                     const int *rbin, const double *g_bins, double radius, int k, int64_t n_q,
+                     const double *qx, const double *qw, const int *qbin, double *out,
+                     double *r_used, int64_t *n_used);
+
 /* ---------------- Metrics ---------------- */
 void orc_image_error(int64_t n, const double *img, const double *ref, double *rmse, double *rel_rmse,
                      double *psnr);

@@ -164,6 +164,9 @@ def lib():
                                      C.POINTER(C.c_int), dp, dp, dp, dp]
         L.orc_fi_pixels.argtypes = [C.POINTER(Scene), C.POINTER(CameraS), C.POINTER(FiParams),
                                     C.POINTER(Cache), C.POINTER(Field), C.c_int64, i64p, dp]
+        L.orc_pm_scores.argtypes = [C.POINTER(Scene), C.c_int64, dp, dp, dp]
+        L.orc_pm_estimate.argtypes = [C.c_int64, dp, dp, dp, ip, dp, C.c_double, C.c_int,
+                                      C.c_int64, dp, dp, ip, dp, dp, i64p]
         L.orc_image_error.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.orc_num_threads.restype = C.c_int
         _lib = L
@@ -526,6 +529,29 @@ def fi_pixels(scene: OracleScene, cam, params: FiParams, pixels=None,
                         _ptr(pixels, i64p), _ptr(out))
     del keep
     return out
+
+
+def pm_scores(scene: OracleScene, x, power) -> np.ndarray:
+    """Collision-estimator scores Phi / sigma_t(x) of photon records."""
+    x, power = _d(x).reshape(-1, 3), _d(power).reshape(-1, 3)
+    out = np.zeros_like(power)
+    lib().orc_pm_scores(scene.ref, x.shape[0], _ptr(x), _ptr(power), _ptr(out))
+    return out
+
+
+def pm_estimate(rec_x, rec_w, rec_s, rec_bin, g_bins, radius, k, qx, qw, qbin):
+    """Eq. (5) estimates at the queries; returns (L [n, 3], r_used [n], n_used [n])."""
+    rx, rw, rs = (_d(a).reshape(-1, 3) for a in (rec_x, rec_w, rec_s))
+    rb = np.ascontiguousarray(rec_bin, dtype=np.int32)
+    qx, qw = _d(qx).reshape(-1, 3), _d(qw).reshape(-1, 3)
+    qb = np.ascontiguousarray(qbin, dtype=np.int32)
+    gb = _d(g_bins)
+    n = qx.shape[0]
+    out, r_used, n_used = np.zeros((n, 3)), np.zeros(n), np.zeros(n, dtype=np.int64)
+    lib().orc_pm_estimate(rx.shape[0], _ptr(rx), _ptr(rw), _ptr(rs), _ptr(rb, ip), _ptr(gb),
+                          float(radius), int(k), n, _ptr(qx), _ptr(qw), _ptr(qb, ip), _ptr(out),
+                          _ptr(r_used), _ptr(n_used, i64p))
+    return out, r_used, n_used
 
 
 def image_error(img, ref):
