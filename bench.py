@@ -68,6 +68,12 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64-job launch")
     ap.add_argument("--no-first-interaction", action="store_true",
                     help="skip the Algorithm 2 renderer timings")
+    ap.add_argument("--no-photon-map", action="store_true",
+                    help="skip the photon-map (Eq. 5) training timings")
+    ap.add_argument("--pm-radius", type=float, default=0.08,
+                    help="final KNN query radius of the photon-map schedule (cube units)")
+    ap.add_argument("--pm-grid", type=int, default=64)
+    ap.add_argument("--pm-steps", type=int, default=10)
     ap.add_argument("--strategy", default="auto", choices=["auto", "fused", "wavefront", "wavefront_serial"],
                     help="form of the field-lit render")
     ap.add_argument("--batch-steps", type=int, default=10)
@@ -264,6 +270,8 @@ def main():
 
     if fi_info is not None:
         result["first_interaction"] = fi_info
+    if not args.no_photon_map:
+        result["photon_map_training"] = photon_map_bench(ctx, args)
     if not args.no_batch:
         result["batch"] = batch_bench(args)
 
@@ -337,6 +345,51 @@ def first_interaction_bench(ctx, cam, rc, args):
                                         "path_tracer_L": 57.97, "speedup_L": 4.58,
                                         "note": "720p, 1 spp, RTX 3090, averages over seven "
                                                 "datasets' fly-throughs: context only"}}
+
+
+def photon_map_bench(ctx, args):
+    """Training on the photon-map targets of Eq. (5) (Section 3.3) with the staggered KNN schedule
+    of Section 3.5.2: the map of the benchmark trace (HG bins and grid cells), K = 1024, batches
+    of 2^16 as in the paper.  One step = batch, KNN estimates, Eq. (6), forward/backward, Adam.
+    Timed at each radius of the schedule; the schedule's time over 3000 steps (36/27/27/10 % of
+    them at radius/8, /4, /2, /1) is compared with 3000 steps at the final radius (the naive
+    schedule), the comparison of the paper's Figure 10.  Trains a separate field slot."""
+    import torch
+    from paper_2304_07338_amd import _ffi
+    from paper_2304_07338_amd.pfn import FieldConfig, TrainConfig
+    t0 = time.time()
+    ctx.photon_map_build(args.pm_grid)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    ctx.field_select(1)
+    ctx.field_init(FieldConfig(), seed=9)
+    stages = []
+    for frac, share in ((0.125, 0.36), (0.25, 0.27), (0.5, 0.27), (1.0, 0.10)):
+        r = args.pm_radius * frac
+        cfg = TrainConfig(steps=args.pm_steps, log2_batch=16, precision="f16", seed=13,
+                          target="photon_map", knn_k=1024, radius=r, staggered=False)
+        ctx.train_field(TrainConfig(**{**cfg.__dict__, "steps": 2}))
+        torch.cuda.synchronize()
+        ctx.timing_reset()
+        ctx.timing_enable(True)
+        ts = time.perf_counter()
+        ctx.train_field(cfg)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ts) * 1000.0 / cfg.steps
+        est_ms = ctx.timing_get(_ffi.TK_PM_ESTIMATE)[0] / cfg.steps
+        ctx.timing_enable(False)
+        stages.append({"radius": round(r, 5), "share": share, "ms_per_step": round(ms, 4),
+                       "knn_ms_per_step": round(est_ms, 4)})
+        log(f"[pmap] radius {r:.4f}: {ms:.3f} ms per step ({est_ms:.3f} ms of KNN estimates)")
+    ctx.field_select(0)
+    staggered_s = sum(st["share"] * 3000 * st["ms_per_step"] for st in stages) / 1000.0
+    naive_s = 3000 * stages[-1]["ms_per_step"] / 1000.0
+    log(f"[pmap] 3000 steps: staggered {staggered_s:.2f} s, naive {naive_s:.2f} s")
+    return {"workload": "c2 trace (2^22 photons, 5 HG bins), K = 1024, batch 2^16",
+            "grid": args.pm_grid, "build_s": round(build_s, 3), "stages": stages,
+            "train_3000_steps_s": {"staggered": round(staggered_s, 3),
+                                   "naive": round(naive_s, 3),
+                                   "speedup": round(naive_s / staggered_s, 3)}}
 
 
 def batch_bench(args):

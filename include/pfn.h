@@ -114,6 +114,40 @@ pfn_status pfn_set_cache(pfn_context *ctx, const float *dev_in, int n_bins,
                          const float *host_g_bins, int res, double kappa);
 pfn_status pfn_cache_info(pfn_context *ctx, int *host_n_bins, int *host_res, double *host_kappa);
 
+/* Photon map and the radiance estimate of Eq. (5) (Section 3.3).  The map holds photon records
+ * counting-sorted by (HG bin, cell of a uniform grid_res^3 grid over the unit cube); each keeps
+ * its position, incident direction and the collision-estimator score Phi / sigma_t(x) (RGB, the
+ * same normalisation as the isotropic cache, so that g = 0 reproduces the cache's estimate with
+ * a sphere kernel).  The map is a snapshot: later traces or scene changes do not alter it.
+ * pfn_photon_map_build takes the records of the last trace (its HG bins); pfn_photon_map_set
+ * takes n records from device arrays (positions in [0,1]^3, unit incident directions and
+ * incident powers [n][3], bins in [0, n_bins); records with a bin outside that range are
+ * skipped).  Both need the volume and transfer function (for sigma_t) and synchronise.
+ * grid_res in [1, 128]; device memory: 36 B per record plus 4 B x (n_bins grid_res^3 + 1). */
+pfn_status pfn_photon_map_build(pfn_context *ctx, int grid_res);
+pfn_status pfn_photon_map_set(pfn_context *ctx, const float *dev_x, const float *dev_w,
+                              const float *dev_power, const int32_t *dev_bin, uint64_t n,
+                              int n_bins, const float *host_g_bins, int grid_res);
+/* Copies of the map: dev_cell_start (n_bins grid_res^3 + 1 entries: the first record of every
+ * key (bin, z, y, x), x fastest, then the total) and up to `capacity` sorted records
+ * (position, direction, score [n][3]); records of one cell are in no particular order.  Any
+ * output may be NULL; *host_n receives the record count.  Synchronises. */
+pfn_status pfn_photon_map_get(pfn_context *ctx, uint32_t *dev_cell_start, size_t n_start,
+                              float *dev_pos, float *dev_dir, float *dev_score,
+                              uint64_t capacity, uint64_t *host_n);
+/* Eq. (5) at n queries (position [n][3], unit direction of the scattered light [n][3] (toward
+ * the viewer, as for the field), HG bin [n]) over the map's records of the query's bin:
+ *   L = sum_n p_g(w_n . w) score_n / ((4/3) pi r^3), g the bin's anisotropy;
+ *   k = 0: every record within `radius`, r = radius;
+ *   k > 0: the k nearest records within `radius` (K-nearest query with a maximum radius), r the
+ *          distance to the farthest of them (all records within `radius` if there are at most
+ *          k; none gives 0).
+ * Writes rgb [n][3] and, if not NULL, r [n] and the record count [n].  More than 256 records at
+ * one distance (to 2^-40 of the radius) at the K-th place are cut to 256.  radius in (0, 2]. */
+pfn_status pfn_photon_map_estimate(pfn_context *ctx, const float *dev_xyz, const float *dev_dir,
+                                   const int32_t *dev_bin, int64_t n, float radius, int k,
+                                   float *dev_rgb, float *dev_r, int32_t *dev_count);
+
 /* ------------------------------------------------------------------ 2. photon field */
 typedef struct {
   int levels;          /* grid levels (1..16) */
@@ -159,14 +193,27 @@ typedef struct {
   int decay_start, decay_interval;
   pfn_dtype precision;  /* F16 or BF16 matrix cores, or F32 */
   uint64_t seed;
+  int target;           /* 0: the photon cache (gather); 1: the photon map, Eq. (5) */
+  int knn_k;            /* photon-map targets: K nearest (0: every record within the radius) */
+  float radius;         /* photon-map targets: the final (maximum) query radius, cube units */
+  int staggered;        /* photon-map targets: 1 = the staggered schedule of Section 3.5.2 */
 } pfn_train_params;
 
 /* Section 3.5: each step draws a fresh batch (uniform x, uniform direction, g from the cache
- * bins; target = Eq. 6 of the cache value / kappa), runs forward, L2 loss, backward and Adam.
+ * bins), takes its targets, runs forward, L2 loss, backward and Adam.  Targets are Eq. (6) of
+ * value / kappa (kappa: the cache maximum), the value being
+ *   target 0: the cache gather at x in the sample's bin;
+ *   target 1: the photon-map estimate of Eq. (5) at (x, direction) in the sample's bin, with
+ *     knn_k and the step's radius: `radius` throughout, or with `staggered` the radii
+ *     radius * {1/8, 1/4, 1/2, 1} over steps [0, 36 %), [36 %, 63 %), [63 %, 90 %),
+ *     [90 %, 100 %) (the proportions of the paper's Table 1); the map (pfn_photon_map_build or
+ *     _set) must hold the cache's HG bins.
  * Requires a cache and an initialised field.  host_loss_history (steps floats) may be NULL.
  * Synchronises. */
 pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *params,
                            float *host_loss_history);
+/* The photon-map query radius that pfn_train_field uses at `step` (host only, no context). */
+pfn_status pfn_train_step_radius(const pfn_train_params *params, int step, float *host_radius);
 /* The training-batch generator alone (for checking): step `step`'s n samples. */
 pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
                            float *dev_xyz, float *dev_dir, float *dev_g, int32_t *dev_bin,
@@ -300,7 +347,8 @@ pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs,
  * kernels of the wavefront render: 6 = march rounds, 7 = position-encoding launches,
  * 8 = matrix-core field tiles, 9 = pixel resolve (the first-interaction renderer also reports
  * its field pass under 7 and 8 and its resolve under 9); first-interaction renderer:
- * 10 = ray generation, delta-tracking sampling and compaction, 11 = next-event estimation.
+ * 10 = ray generation, delta-tracking sampling and compaction, 11 = next-event estimation;
+ * 12 = photon-map estimate.
  * Ids 0..15 are valid. */
 pfn_status pfn_timing_enable(pfn_context *ctx, int on);
 pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);

@@ -16,7 +16,7 @@ INDIRECT_NONE, INDIRECT_CACHE, INDIRECT_FIELD = 0, 1, 2
 DIRECT_SHADOW_RAYS, DIRECT_LIGHT_VOLUME = 0, 1
 TK_MARCH, TK_TRACE, TK_TRAIN, TK_PT, TK_QUERY, TK_ADAM = 0, 1, 2, 3, 4, 5
 TK_WF_MARCH, TK_WF_ENCODE, TK_WF_FIELD, TK_WF_RESOLVE = 6, 7, 8, 9
-TK_FI_SAMPLE, TK_FI_NEE = 10, 11
+TK_FI_SAMPLE, TK_FI_NEE, TK_PM_ESTIMATE = 10, 11, 12
 
 
 class PointLight(C.Structure):
@@ -48,7 +48,8 @@ class TrainParams(C.Structure):
     _fields_ = [("steps", C.c_int), ("log2_batch", C.c_int), ("lr", C.c_float),
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("decay", C.c_float), ("decay_start", C.c_int), ("decay_interval", C.c_int),
-                ("precision", C.c_int), ("seed", C.c_uint64)]
+                ("precision", C.c_int), ("seed", C.c_uint64), ("target", C.c_int),
+                ("knn_k", C.c_int), ("radius", C.c_float), ("staggered", C.c_int)]
 
 
 class CameraS(C.Structure):
@@ -101,6 +102,14 @@ SIGNATURES = {
     "pfn_render_frame": (C.c_int, [ctxp, C.POINTER(CameraS), C.POINTER(RenderParams), vp]),
     "pfn_render_first_interaction": (C.c_int, [ctxp, C.POINTER(CameraS), C.POINTER(RenderParams),
                                                vp]),
+    "pfn_photon_map_build": (C.c_int, [ctxp, C.c_int]),
+    "pfn_train_step_radius": (C.c_int, [C.POINTER(TrainParams), C.c_int, C.POINTER(C.c_float)]),
+    "pfn_photon_map_set": (C.c_int, [ctxp, vp, vp, vp, vp, C.c_uint64, C.c_int,
+                                     C.POINTER(C.c_float), C.c_int]),
+    "pfn_photon_map_get": (C.c_int, [ctxp, vp, C.c_size_t, vp, vp, vp, C.c_uint64,
+                                     C.POINTER(C.c_uint64)]),
+    "pfn_photon_map_estimate": (C.c_int, [ctxp, vp, vp, vp, C.c_int64, C.c_float, C.c_int, vp,
+                                          vp, vp]),
     "pfn_render_batch": (C.c_int, [ctxp, C.POINTER(RenderJob), C.c_int]),
     "pfn_render_path_traced": (C.c_int, [ctxp, C.POINTER(CameraS), C.c_int, C.c_int, C.c_float,
                                          C.c_int, C.c_int, C.c_uint64, vp]),

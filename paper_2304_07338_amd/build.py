@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpfn.so")
 SOURCES = ["api.cpp", "volume.hip", "march.hip", "wavefront.hip", "first_interaction.hip", "field.hip",
-           "trace.hip", "train.hip", "pt.hip"]
+           "trace.hip", "train.hip", "pt.hip", "photonmap.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
          "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function", "-Wno-unused-variable",

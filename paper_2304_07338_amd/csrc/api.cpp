@@ -154,6 +154,8 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   dev_free(ctx->counters);
   dev_free(ctx->queues);
   wf_release(ctx->wf);
+  pm_release(ctx->pmap);
+  dev_free(ctx->pm_batch);
   for (auto &g : ctx->graphs) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -822,6 +824,73 @@ extern "C" pfn_status pfn_render_batch(pfn_context *ctx, const pfn_render_job *j
   if (st) return st;
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   return run_march(ctx, jobs, n_jobs, ctx->tile);
+}
+
+// ------------------------------------------------------------------ photon map (Eq. 5)
+extern "C" pfn_status pfn_photon_map_build(pfn_context *ctx, int grid_res) {
+  CHECK_CTX(ctx);
+  ARG(grid_res >= 1 && grid_res <= 128, "grid_res in [1, 128]");
+  pfn_status st = need_scene(ctx);
+  if (st) return st;
+  if (ctx->rec_photons == 0) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no trace yet");
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  PmSrcHost src{ctx->rec_x, ctx->rec_w, ctx->rec_p, ctx->rec_bin, ctx->rec_cnt, ctx->rec_maxrec,
+                ctx->rec_photons * (uint64_t)ctx->rec_maxrec};
+  return pm_build(ctx, src, ctx->cache_bins, ctx->g_bins, grid_res);
+}
+
+extern "C" pfn_status pfn_photon_map_set(pfn_context *ctx, const float *x, const float *w,
+                                         const float *power, const int32_t *bin, uint64_t n,
+                                         int n_bins, const float *g_bins, int grid_res) {
+  CHECK_CTX(ctx);
+  ARG(grid_res >= 1 && grid_res <= 128, "grid_res in [1, 128]");
+  ARG(n_bins >= 1 && n_bins <= 8 && g_bins, "1 to 8 HG bins");
+  ARG(n < ((uint64_t)1 << 32), "fewer than 2^32 records");
+  ARG(n == 0 || (x && w && power && bin), "NULL record array");
+  for (int i = 0; i < n_bins; ++i)
+    ARG(std::isfinite(g_bins[i]) && std::fabs(g_bins[i]) <= 0.95f, "|g| <= 0.95");
+  pfn_status st = need_scene(ctx);
+  if (st) return st;
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  PmSrcHost src{x, w, power, bin, nullptr, 1, n};
+  return pm_build(ctx, src, n_bins, g_bins, grid_res);
+}
+
+extern "C" pfn_status pfn_photon_map_get(pfn_context *ctx, uint32_t *cell_start, size_t n_start,
+                                         float *pos, float *dir, float *score, uint64_t capacity,
+                                         uint64_t *host_n) {
+  CHECK_CTX(ctx);
+  if (!ctx->pmap.valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon map");
+  const PhotonMapState &m = ctx->pmap;
+  const size_t keys = (size_t)m.n_bins * m.grid * m.grid * m.grid + 1;
+  ARG(!cell_start || n_start == keys, "cell_start must hold n_bins * grid^3 + 1 entries");
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  if (cell_start)
+    PFN_HIP(ctx, hipMemcpyAsync(cell_start, m.start, keys * sizeof(uint32_t),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+  const uint64_t n = std::min<uint64_t>(m.n, capacity);
+  PFN_HIP(ctx, pm_launch_unpack(ctx, pos, dir, score, n));
+  PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (host_n) *host_n = m.n;
+  return PFN_OK;
+}
+
+extern "C" pfn_status pfn_photon_map_estimate(pfn_context *ctx, const float *xyz,
+                                              const float *dir, const int32_t *bin, int64_t n,
+                                              float radius, int k, float *rgb, float *r_out,
+                                              int32_t *n_out) {
+  CHECK_CTX(ctx);
+  if (!ctx->pmap.valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon map");
+  ARG(n >= 0 && n < ((int64_t)1 << 31), "n in [0, 2^31)");
+  ARG(n == 0 || (xyz && dir && bin && rgb), "NULL argument");
+  ARG(std::isfinite(radius) && radius > 0.0f && radius <= 2.0f, "radius in (0, 2]");
+  ARG(k >= 0 && k <= (1 << 20), "k in [0, 2^20]");
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  const int tslot = timing_begin(ctx);
+  PFN_HIP(ctx, pm_launch_estimate(ctx, xyz, dir, bin, n, radius, k, rgb, r_out, n_out,
+                                  ctx->stream));
+  timing_end(ctx, tslot, TK_PM_ESTIMATE);
+  return PFN_OK;
 }
 
 // ------------------------------------------------------------------ timing

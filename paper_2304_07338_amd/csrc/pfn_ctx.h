@@ -42,6 +42,29 @@ struct TileConfig {
 
 // Autotuner result for one batch shape and render form (fused with or without graph replay,
 // wavefront, serial wavefront).
+// Photon map (Eq. 5): records counting-sorted by (HG bin, cell of a grid^3 grid), each as
+// position + red score, direction + green score, blue score (score = Phi / sigma_t).
+#define PM_SCAN_DEPTH 3
+struct PhotonMapState {
+  float4 *ra = nullptr, *rb = nullptr;
+  float *rc = nullptr;
+  uint32_t *start = nullptr;   // first record of every key, n_bins * grid^3 + 1 entries
+  uint32_t *counts = nullptr, *keys = nullptr;
+  uint32_t *scan_tmp[PM_SCAN_DEPTH] = {};
+  uint64_t n = 0, rec_cap = 0, slot_cap = 0, key_cap = 0;
+  int grid = 0, n_bins = 0;
+  float g_bins[8] = {};
+  bool valid = false;
+};
+// Records to build a photon map from: trace slots (cnt, maxrec) or a dense array (cnt NULL).
+struct PmSrcHost {
+  const float *x, *w, *p;
+  const int32_t *bin;
+  const uint8_t *cnt;
+  int maxrec;
+  uint64_t n_slots;
+};
+
 struct TunedEntry {
   std::vector<unsigned char> key;
   TileConfig best;
@@ -142,6 +165,9 @@ struct pfn_context {
   std::vector<TunedEntry> tuned;  // autotuner cache, one entry per batch shape and render form
   int strategy = PFN_STRATEGY_AUTO;  // field renders: fused kernel or wavefront rounds
   WfState wf;
+  PhotonMapState pmap;
+  float *pm_batch = nullptr;  // training batch with photon-map targets
+  size_t pm_batch_cap = 0;
 
   // training activations / deltas (neuron-major, 16-bit or FP32)
   void *train_act = nullptr;
@@ -169,7 +195,7 @@ struct pfn_context {
 enum TimedKernel {
   TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5,
   TK_WF_MARCH = 6, TK_WF_ENCODE = 7, TK_WF_FIELD = 8, TK_WF_RESOLVE = 9, TK_FI_SAMPLE = 10,
-  TK_FI_NEE = 11
+  TK_FI_NEE = 11, TK_PM_ESTIMATE = 12
 };
 
 // Error helpers
@@ -206,6 +232,13 @@ void field_params_changed(FieldSlot &f);
 pfn_status alloc_cache(pfn_context *ctx, int n_bins, int res);
 pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, const TileConfig &tc,
                      bool first_interaction = false);
+// Photon map: build (synchronises) and the Eq. (5) estimate kernel.
+pfn_status pm_build(pfn_context *ctx, const PmSrcHost &src, int n_bins, const float *g_bins, int G);
+hipError_t pm_launch_estimate(pfn_context *ctx, const float *xyz, const float *dir,
+                              const int32_t *bin, int64_t n, float radius, int k, float *out,
+                              float *r_out, int32_t *n_out, hipStream_t st);
+hipError_t pm_launch_unpack(pfn_context *ctx, float *pos, float *dir, float *score, uint64_t n);
+void pm_release(PhotonMapState &m);
 // First-interaction renderer (one job): sampling, direct light, field pass and resolve.
 pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob job, int indirect,
                                  int prec, int slot, const FieldDev &fd_host);

@@ -898,6 +898,26 @@ extern "C" pfn_status pfn_field_adam_step(pfn_context *ctx, const float *dev_gra
   return PFN_OK;
 }
 
+__global__ void log_target_kernel(const float *__restrict__ v, float *__restrict__ tgt, int64_t n3,
+                                  float inv_kappa, float psi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n3) tgt[i] = log_target(v[i] * inv_kappa, psi);
+}
+
+// Query radius of step s: the final radius, or the staggered schedule (fractions of Table 1).
+static float step_radius(const pfn_train_params *p, int s) {
+  if (!p->staggered) return p->radius;
+  const double f = (double)s / (double)p->steps;
+  const double r = f < 0.36 ? 0.125 : f < 0.63 ? 0.25 : f < 0.90 ? 0.5 : 1.0;
+  return (float)(r * (double)p->radius);
+}
+
+extern "C" pfn_status pfn_train_step_radius(const pfn_train_params *p, int step, float *radius) {
+  if (!p || !radius || p->steps < 1 || step < 0 || step >= p->steps) return PFN_ERR_INVALID_ARG;
+  *radius = step_radius(p, step);
+  return PFN_OK;
+}
+
 extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *p, float *hist) {
   if (!ctx) return PFN_ERR_INVALID_ARG;
   if (!p) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "params are NULL");
@@ -911,6 +931,20 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
   if (!(p->precision == PFN_F32 || p->precision == PFN_F16 || p->precision == PFN_BF16))
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad precision");
   if (!ctx->cache_valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon cache");
+  if (p->target != 0 && p->target != 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "target: 0 (cache) or 1 (photon map)");
+  const bool map_targets = p->target == 1;
+  if (map_targets) {
+    if (!(std::isfinite(p->radius) && p->radius > 0.0f && p->radius <= 2.0f))
+      return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "radius in (0, 2]");
+    if (p->knn_k < 0 || p->knn_k > (1 << 20))
+      return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "knn_k in [0, 2^20]");
+    const PhotonMapState &m = ctx->pmap;
+    if (!m.valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon map");
+    bool same = m.n_bins == ctx->cache_bins;
+    for (int b = 0; same && b < m.n_bins; ++b) same = m.g_bins[b] == ctx->g_bins[b];
+    if (!same) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "photon map and cache HG bins differ");
+  }
   FieldSlot &f = ctx->fields[ctx->cur_field];
   pfn_status st = check_training_field(ctx, f);
   if (st) return st;
@@ -919,6 +953,17 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
   const int64_t n = (int64_t)1 << p->log2_batch;
   st = ensure_train_buffers(ctx, f, prec, n);
   if (st) return st;
+  if (map_targets && ctx->pm_batch_cap < (size_t)n) {
+    if (ctx->pm_batch) (void)hipFree(ctx->pm_batch);
+    ctx->pm_batch = nullptr;
+    ctx->pm_batch_cap = 0;
+    // xyz, dir, value, target (3 floats each), g (1 float), bin (1 int)
+    PFN_HIP(ctx, hipMalloc((void **)&ctx->pm_batch, sizeof(float) * 14 * (size_t)n));
+    ctx->pm_batch_cap = (size_t)n;
+  }
+  float *b_xyz = ctx->pm_batch, *b_dir = b_xyz + 3 * n, *b_val = b_dir + 3 * n,
+        *b_tgt = b_val + 3 * n, *b_g = b_tgt + 3 * n;
+  int32_t *b_bin = reinterpret_cast<int32_t *>(b_g + n);
   st = ensure_scratch(ctx, sizeof(double) * (size_t)p->steps + 64);
   if (st) return st;
   double *loss_dev = (double *)ctx->scratch;
@@ -929,7 +974,24 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
     st = refresh_train_images(ctx, f, prec);
     if (st) return st;
     SampleSrc src = make_src(ctx, p->seed, s, f.desc.psi);
-    st = run_fb(ctx, f, prec, n, true, src, nullptr, nullptr, nullptr, nullptr, loss_dev + s);
+    if (map_targets) {
+      // the step's batch (the same samples as the cache targets would use), its Eq. (5)
+      // estimates and their Eq. (6) encoding
+      const unsigned nb = (unsigned)((n + 255) / 256);
+      hipLaunchKernelGGL(train_batch_kernel, dim3(nb), dim3(256), 0, ctx->stream, src, n, b_xyz,
+                         b_dir, b_g, b_bin, nullptr);
+      PFN_HIP(ctx, hipGetLastError());
+      const int ts = timing_begin(ctx);
+      PFN_HIP(ctx, pm_launch_estimate(ctx, b_xyz, b_dir, b_bin, n, step_radius(p, s), p->knn_k,
+                                      b_val, nullptr, nullptr, ctx->stream));
+      timing_end(ctx, ts, TK_PM_ESTIMATE);
+      hipLaunchKernelGGL(log_target_kernel, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0,
+                         ctx->stream, b_val, b_tgt, 3 * n, src.inv_kappa, src.psi);
+      PFN_HIP(ctx, hipGetLastError());
+      st = run_fb(ctx, f, prec, n, false, src, b_xyz, b_dir, b_g, b_tgt, loss_dev + s);
+    } else {
+      st = run_fb(ctx, f, prec, n, true, src, nullptr, nullptr, nullptr, nullptr, loss_dev + s);
+    }
     if (st) return st;
     double lr = p->lr;
     if (s >= p->decay_start)

@@ -77,11 +77,28 @@ class TrainConfig:
     decay_interval: int = 25
     precision: str = "f16"
     seed: int = 0
+    target: str = "cache"   # or "photon_map" (Eq. 5)
+    knn_k: int = 0
+    radius: float = 0.05
+    staggered: bool = False
 
     def struct(self) -> _ffi.TrainParams:
         return _ffi.TrainParams(self.steps, self.log2_batch, self.lr, self.beta1, self.beta2,
                                 self.eps, self.decay, self.decay_start, self.decay_interval,
-                                DTYPES[self.precision], self.seed)
+                                DTYPES[self.precision], self.seed,
+                                {"cache": 0, "photon_map": 1}[self.target], self.knn_k,
+                                self.radius, int(self.staggered))
+
+
+def train_step_radius(cfg: "TrainConfig", step: int) -> float:
+    """The photon-map query radius that training uses at `step` (host only)."""
+    lib = _ffi.load()
+    r = C.c_float()
+    p = cfg.struct()
+    st = lib.pfn_train_step_radius(C.byref(p), step, C.byref(r))
+    if st != 0:
+        raise PfnError(st, "pfn_train_step_radius: bad arguments")
+    return r.value
 
 
 def camera_struct(cam) -> _ffi.CameraS:
@@ -208,6 +225,51 @@ class Context:
                                           capacity, C.byref(n)))
         k = n.value
         return dict(x=x[:k], w=w[:k], power=p[:k], bin=b[:k], photon=ph[:k])
+
+    # -------------------------------------------------------------- photon map (Eq. 5)
+    def photon_map_build(self, grid_res: int = 64):
+        """Photon map from the last trace's records (sorted by HG bin and grid cell)."""
+        self._ok(self.lib.pfn_photon_map_build(self.h, grid_res))
+
+    def photon_map_set(self, x, w, power, bins, g_bins, grid_res: int = 64):
+        """Photon map from caller records (device tensors [n, 3] float32 and [n] int32)."""
+        import torch
+        n = int(x.shape[0])
+        for t, name in ((x, "x"), (w, "w"), (power, "power")):
+            _check(t, torch.float32, 3 * n, name)
+        _check(bins, torch.int32, n, "bins")
+        g = (C.c_float * len(g_bins))(*[float(v) for v in g_bins])
+        self._ok(self.lib.pfn_photon_map_set(self.h, _ptr(x), _ptr(w), _ptr(power), _ptr(bins), n,
+                                             len(g_bins), g, grid_res))
+
+    def photon_map_get(self, n_keys: int, capacity: int):
+        import torch
+        dev = f"cuda:{self.device}"
+        start = torch.empty(n_keys, dtype=torch.int32, device=dev)
+        pos = torch.empty((capacity, 3), dtype=torch.float32, device=dev)
+        dirs = torch.empty((capacity, 3), dtype=torch.float32, device=dev)
+        score = torch.empty((capacity, 3), dtype=torch.float32, device=dev)
+        n = C.c_uint64()
+        self._ok(self.lib.pfn_photon_map_get(self.h, _ptr(start), n_keys, _ptr(pos), _ptr(dirs),
+                                             _ptr(score), capacity, C.byref(n)))
+        k = min(n.value, capacity)
+        return dict(start=start, pos=pos[:k], dir=dirs[:k], score=score[:k], n=n.value)
+
+    def photon_map_estimate(self, xyz, dirs, bins, radius: float, k: int = 0):
+        """Eq. (5) at the queries: returns (rgb [n, 3], r [n], count [n])."""
+        import torch
+        n = int(xyz.shape[0])
+        _check(xyz, torch.float32, 3 * n, "xyz")
+        _check(dirs, torch.float32, 3 * n, "dirs")
+        _check(bins, torch.int32, n, "bins")
+        dev = f"cuda:{self.device}"
+        rgb = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        r = torch.empty(n, dtype=torch.float32, device=dev)
+        cnt = torch.empty(n, dtype=torch.int32, device=dev)
+        self._ok(self.lib.pfn_photon_map_estimate(self.h, _ptr(xyz), _ptr(dirs), _ptr(bins), n,
+                                                  float(radius), int(k), _ptr(rgb), _ptr(r),
+                                                  _ptr(cnt)))
+        return rgb, r, cnt
 
     def cache_info(self):
         nb, res, kappa = C.c_int(), C.c_int(), C.c_double()

@@ -1,0 +1,245 @@
+"""Parity of the HIP photon map (counting sort by HG bin and grid cell) and of its Eq. (5)
+radiance estimates (fixed radius and K nearest) with the FP64 oracle, on seeded synthetic
+photon records given to both sides.
+
+Index work is exact: the first record of every (bin, cell) key equals numpy's counting of the
+FP32 keys, and every cell holds exactly its records (their order inside a cell is free).  The
+estimates compare record counts exactly and values to FP32 accumulation (1e-4 relative),
+except for queries where a record lies within FP32 rounding of the radius or of the K-th
+distance (at most 1 % of the queries)."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import gpu_context, oracle_scene, say, scene_arrays
+
+pytestmark = pytest.mark.gpu
+
+G_BINS = [-0.5, 0.0, 0.6]
+
+
+def _unit(v):
+    return v / np.linalg.norm(v, axis=-1, keepdims=True)
+
+
+def _records(n, seed):
+    """Clustered positions (half uniform, half around three centres), unit directions,
+    positive powers, bins in [0, 3) with a few outside that range (skipped by the map)."""
+    rng = np.random.default_rng(seed)
+    m = n // 2
+    centres = np.array([[0.3, 0.4, 0.5], [0.7, 0.6, 0.4], [0.5, 0.5, 0.7]])
+    c = centres[rng.integers(0, 3, n - m)]
+    x = np.concatenate([rng.uniform(0, 1, (m, 3)),
+                        np.clip(c + rng.normal(scale=0.06, size=(n - m, 3)), 0.0, 1.0)])
+    w = _unit(rng.normal(size=(n, 3)))
+    p = rng.uniform(0.01, 1.0, (n, 3))
+    b = rng.integers(0, 3, n)
+    b[rng.random(n) < 0.01] = 5
+    b[rng.random(n) < 0.01] = -1
+    return (x.astype(np.float32), w.astype(np.float32), p.astype(np.float32),
+            b.astype(np.int32))
+
+
+@pytest.fixture(scope="module")
+def pm(orc):
+    import torch
+    wl_, vol, tf, lights = scene_arrays("c0")
+    # a uniform medium keeps every record's sigma_t positive
+    vol = torch.full_like(vol, 0.5)
+    ctx = gpu_context(vol, tf, lights)
+    os_ = oracle_scene(orc, vol, tf, lights)
+    x, w, p, b = _records(200000, 1)
+    dev = "cuda:0"
+    T = lambda a: torch.tensor(a, device=dev).contiguous()
+    G = 32
+    ctx.photon_map_set(T(x), T(w), T(p), T(b), G_BINS, grid_res=G)
+    keep = (b >= 0) & (b < 3)
+    scores = orc.pm_scores(os_, x[keep].astype(np.float64), p[keep].astype(np.float64))
+    return dict(ctx=ctx, os=os_, x=x, w=w, p=p, b=b, keep=keep, G=G, scores=scores, T=T)
+
+
+def test_counting_sort_is_exact(pm):
+    x, b, keep, G = pm["x"], pm["b"], pm["keep"], pm["G"]
+    cell = np.clip(np.floor(x * np.float32(G)).astype(np.int64), 0, G - 1)
+    key = ((b.astype(np.int64) * G + cell[:, 2]) * G + cell[:, 1]) * G + cell[:, 0]
+    n_keys = 3 * G ** 3
+    counts = np.bincount(key[keep], minlength=n_keys)
+    start = np.concatenate([[0], np.cumsum(counts)])
+    got = pm["ctx"].photon_map_get(n_keys + 1, int(keep.sum()))
+    assert got["n"] == keep.sum()
+    np.testing.assert_array_equal(got["start"].cpu().numpy().astype(np.int64), start)
+    # every cell holds exactly its records: compare the records sorted by (key, position)
+    pos = got["pos"].cpu().numpy()
+    gkey = np.repeat(np.arange(n_keys), counts)
+    order_g = np.lexsort((pos[:, 2], pos[:, 1], pos[:, 0], gkey))
+    xs, ks = x[keep], key[keep]
+    order_r = np.lexsort((xs[:, 2], xs[:, 1], xs[:, 0], ks))
+    np.testing.assert_array_equal(pos[order_g], xs[order_r])
+    np.testing.assert_array_equal(got["dir"].cpu().numpy()[order_g], pm["w"][keep][order_r])
+    sc = got["score"].cpu().numpy()[order_g]
+    np.testing.assert_allclose(sc, pm["scores"][order_r], rtol=2e-6)
+
+
+def _queries(n, seed):
+    rng = np.random.default_rng(seed)
+    qx = rng.uniform(0.05, 0.95, (n, 3)).astype(np.float32)
+    qw = _unit(rng.normal(size=(n, 3))).astype(np.float32)
+    qb = rng.integers(0, 3, n).astype(np.int32)
+    return qx, qw, qb
+
+
+def _compare(pm, orc, qx, qw, qb, radius, k, what, rtol=1e-4, min_frac=0.99, recs=None):
+    ctx, T = pm["ctx"], pm["T"]
+    rgb, r, cnt = ctx.photon_map_estimate(T(qx), T(qw), T(qb), radius, k)
+    rgb, r, cnt = rgb.cpu().numpy(), r.cpu().numpy(), cnt.cpu().numpy()
+    if recs is None:
+        keep = pm["keep"]
+        recs = (pm["x"][keep], pm["w"][keep], pm["scores"], pm["b"][keep])
+    rx, rw, rs, rb = recs
+    ref, r_ref, n_ref = orc.pm_estimate(rx.astype(np.float64), rw.astype(np.float64), rs, rb,
+                                        G_BINS, radius, k, qx.astype(np.float64),
+                                        qw.astype(np.float64), qb)
+    same_n = cnt == n_ref
+    ok = same_n & np.all(np.abs(rgb - ref) <= rtol * np.abs(ref) + 1e-30, axis=1)
+    ok &= np.abs(r - r_ref) <= 1e-5 * np.maximum(r_ref, 1e-30)
+    say(f"  {what}: {ok.sum()} / {ok.size} queries agree, counts {np.median(n_ref):.0f} median, "
+        f"{(n_ref == 0).sum()} empty")
+    assert ok.mean() >= min_frac
+    assert np.median(n_ref) > 0
+    return rgb, ref
+
+
+def test_fixed_radius_estimate(orc, pm):
+    qx, qw, qb = _queries(3000, 2)
+    _compare(pm, orc, qx, qw, qb, 0.06, 0, "fixed radius 0.06")
+
+
+@pytest.mark.parametrize("k,radius", [(64, 0.1), (1024, 0.2), (1024, 0.03)])
+def test_knn_estimate(orc, pm, k, radius):
+    """(1024, 0.03): most queries hold fewer than k records within the radius and take all."""
+    qx, qw, qb = _queries(2000, 3 + k)
+    _compare(pm, orc, qx, qw, qb, radius, k, f"KNN k={k} r_max={radius}")
+
+
+def test_knn_refines_a_crowded_distance_bin(orc, pm):
+    """2000 records within 1e-3 relative of one distance from the query: the first histogram
+    puts them in one or two bins, which are refined before the ranking.  Neighbouring distances
+    are then about 1e-6 apart, a few FP32 roundings, so the K-th and (K+1)-th records may trade
+    places against the FP64 ranking: values agree to 3 / K, counts and radii exactly (1e-5)."""
+    import torch
+    rng = np.random.default_rng(9)
+    n = 2000
+    d = _unit(rng.normal(size=(n, 3)))
+    rho = 0.1 * (1 + 1e-3 * rng.uniform(size=(n, 1)))
+    x = (0.5 + rho * d).astype(np.float32)
+    w = _unit(rng.normal(size=(n, 3))).astype(np.float32)
+    p = rng.uniform(0.1, 1.0, (n, 3)).astype(np.float32)
+    b = np.zeros(n, dtype=np.int32)
+    ctx, T = pm["ctx"], pm["T"]
+    ctx.photon_map_set(T(x), T(w), T(p), T(b), G_BINS, grid_res=8)
+    try:
+        scores = orc.pm_scores(pm["os"], x.astype(np.float64), p.astype(np.float64))
+        qx = np.tile(np.float32([0.5, 0.5, 0.5]), (4, 1))
+        qw = _unit(rng.normal(size=(4, 3))).astype(np.float32)
+        qb = np.zeros(4, dtype=np.int32)
+        for k in (100, 1000, 1999):
+            _compare(pm, orc, qx, qw, qb, 0.2, k, f"crowded shell, k={k}", min_frac=1.0,
+                     recs=(x, w, scores, b), rtol=3.0 / k)
+    finally:
+        keep = pm["keep"]
+        ctx.photon_map_set(T(pm["x"]), T(pm["w"]), T(pm["p"]), T(pm["b"]), G_BINS,
+                           grid_res=pm["G"])
+        assert keep.sum() > 0
+
+
+def test_knn_takes_whole_lattice_shells(orc, pm):
+    h = 0.01
+    ii = np.arange(-3, 4)
+    g = (np.stack(np.meshgrid(ii, ii, ii, indexing="ij"), -1).reshape(-1, 3) * h
+         + 0.5).astype(np.float32)
+    n = g.shape[0]
+    w = np.tile(np.float32([0.0, 0.0, 1.0]), (n, 1))
+    p = np.ones((n, 3), dtype=np.float32)
+    b = np.zeros(n, dtype=np.int32)
+    ctx, T = pm["ctx"], pm["T"]
+    ctx.photon_map_set(T(g), T(w), T(p), T(b), G_BINS, grid_res=16)
+    try:
+        q = T(np.float32([[0.5, 0.5, 0.5]]))
+        qd = T(np.float32([[1.0, 0.0, 0.0]]))
+        qb = T(np.int32([0]))
+        for k, r_exp in ((7, h), (19, h * math.sqrt(2)), (27, h * math.sqrt(3))):
+            rgb, r, cnt = ctx.photon_map_estimate(q, qd, qb, 0.05, k)
+            assert int(cnt[0]) == k
+            assert float(r[0]) == pytest.approx(r_exp, rel=1e-5)
+    finally:
+        ctx.photon_map_set(T(pm["x"]), T(pm["w"]), T(pm["p"]), T(pm["b"]), G_BINS,
+                           grid_res=pm["G"])
+
+
+def test_map_from_a_trace(orc):
+    """The map built from the last trace holds all its records, sorted by bin and cell."""
+    from paper_2304_07338_amd import workloads as wl
+    w, vol, tf, lights = scene_arrays("c0")
+    ctx = gpu_context(vol, tf, lights)
+    st = ctx.trace_photon_cache(1 << 18, wl.C1_G_BINS, cache_res=32, seed=3)
+    ctx.photon_map_build(24)
+    nb = len(wl.C1_G_BINS)
+    got = ctx.photon_map_get(nb * 24 ** 3 + 1, 16)
+    assert got["n"] == st["n_records"]
+    start = got["start"].cpu().numpy().astype(np.int64)
+    assert start[0] == 0 and start[-1] == st["n_records"] and np.all(np.diff(start) >= 0)
+    ctx.close()
+
+
+def _trained_scene():
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import FieldConfig
+    w, vol, tf, lights = scene_arrays("c0")
+    ctx = gpu_context(vol, tf, lights)
+    ctx.trace_photon_cache(1 << 18, wl.C1_G_BINS, cache_res=32, seed=3)
+    ctx.photon_map_build(24)
+    ctx.field_select(0)
+    ctx.field_init(FieldConfig(log2_table=14), seed=2)
+    return ctx
+
+
+@pytest.mark.parametrize("k,staggered", [(0, False), (32, True)])
+def test_training_step_uses_photon_map_targets(k, staggered):
+    """The first step's loss equals the loss of the same batch against Eq. (6) of the map's
+    estimate at the schedule's first radius (computed through the estimate entry point)."""
+    import torch
+    from paper_2304_07338_amd.pfn import TrainConfig, train_step_radius
+    ctx = _trained_scene()
+    nb, res, kappa = ctx.cache_info()
+    radius = 0.4 if staggered else 0.12
+    cfg = TrainConfig(steps=4, log2_batch=12, precision="f32", seed=5, target="photon_map",
+                      knn_k=k, radius=radius, staggered=staggered)
+    xyz, dirs, g, bins, _ = ctx.train_batch(5, 0, 4096)
+    r0 = train_step_radius(cfg, 0)
+    assert r0 == pytest.approx(radius / 8 if staggered else radius)
+    rgb, _, cnt = ctx.photon_map_estimate(xyz, dirs, bins, r0, k)
+    v = rgb.cpu().numpy().astype(np.float64) / kappa
+    psi = 5.0
+    tgt = np.where(v > 10.0 ** -psi, -np.log10(np.maximum(v, 1e-300)) / psi, 1.0)
+    loss_ref, _ = ctx.field_forward_backward(xyz, dirs, g,
+                                             torch.tensor(tgt, dtype=torch.float32,
+                                                          device="cuda:0").contiguous())
+    hist = ctx.train_field(cfg)
+    say(f"  k={k} staggered={staggered}: step-0 loss {hist[0]:.6g} vs {loss_ref:.6g}; "
+        f"records per query median {float(cnt.float().median()):.0f}")
+    assert float(cnt.float().mean()) > 0.5
+    assert hist[0] == pytest.approx(loss_ref, rel=2e-5)
+    assert np.all(np.isfinite(hist))
+    ctx.close()
+
+
+def test_training_on_photon_map_targets_converges():
+    from paper_2304_07338_amd.pfn import TrainConfig
+    ctx = _trained_scene()
+    cfg = TrainConfig(steps=300, log2_batch=14, precision="f16", seed=6, target="photon_map",
+                      knn_k=64, radius=0.12, staggered=True, decay_start=200)
+    hist = ctx.train_field(cfg)
+    say(f"  photon-map targets, 300 steps: loss {hist[:10].mean():.4g} -> {hist[-10:].mean():.4g}")
+    assert hist[-10:].mean() < 0.3 * hist[:10].mean()
+    ctx.close()
