@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--mr-height", type=int, default=1080)
     ap.add_argument("--mr-ref-spp", type=int, default=4096)
     ap.add_argument("--mr-photons", type=int, default=24, help="log2 photons per re-trace")
+    ap.add_argument("--studies", action="store_true",
+                    help="run the phase-awareness and noise studies instead")
+    ap.add_argument("--st-photons", type=int, default=22, help="log2 photons per study trace")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -92,6 +95,9 @@ def main():
 
     if args.matched_rmse:
         print(json.dumps(matched_rmse(args)), flush=True)
+        return
+    if args.studies:
+        print(json.dumps(studies(args)), flush=True)
         return
 
     import numpy as np
@@ -614,6 +620,128 @@ def matched_rmse(args):
                                   "light": round(lat_light, 3)},
         "per_g": per_g,
     }
+
+
+def ssim(img, ref):
+    """Mean SSIM (Gaussian window sigma 1.5, K1 = 0.01, K2 = 0.03) of the luminance (RGB mean)
+    of two images, with the reference's maximum as the dynamic range."""
+    import numpy as np
+    from scipy.ndimage import gaussian_filter
+    a = np.asarray(img, dtype=np.float64).mean(-1)
+    b = np.asarray(ref, dtype=np.float64).mean(-1)
+    L = max(float(b.max()), 1e-30)
+    c1, c2 = (0.01 * L) ** 2, (0.03 * L) ** 2
+    f = lambda x: gaussian_filter(x, 1.5, truncate=3.5)
+    ma, mb = f(a), f(b)
+    va, vb, cab = f(a * a) - ma * ma, f(b * b) - mb * mb, f(a * b) - ma * mb
+    m = ((2 * ma * mb + c1) * (2 * cab + c2)) / ((ma * ma + mb * mb + c1) * (va + vb + c2))
+    return float(m.mean())
+
+
+def studies(args):
+    """Phase-function awareness and stochastic noise (Sections 4.3 and 4.5 of the paper), on the
+    256^3 f32 synthetic scene with 3 lights at 640x480.
+
+    Phase awareness: a field trained on a trace with G = {-0.75, 0, 0.75} renders L_i (the
+    field-lit ray-marched frame minus the direct-only frame) at g in {-0.75, -0.35, 0, 0.35,
+    0.75}; each is compared with the L_i of a separate single-bin photon cache traced at exactly
+    that g (so g = +-0.35 are phases the field never saw).  The error between two independent
+    reference traces at g = 0 is the tracing floor.
+
+    Noise: the Algorithm 2 renderer with the field and the path tracer (at most 16 collisions)
+    at 1, 4 and 8 spp; the noise of each is the RMS difference of two frames with different
+    seeds over sqrt 2, relative to the mean of a 1024-spp path-traced frame."""
+    import numpy as np
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import (Context, FieldConfig, RenderConfig, TrainConfig,
+                                          DIRECT_LIGHT_VOLUME, INDIRECT_CACHE, INDIRECT_FIELD,
+                                          INDIRECT_NONE)
+    w = wl.C1
+    W, H = 640, 480
+    vol, tf, lights = wl.make_scene(w, device="cuda:0")
+    ctx = Context(0)
+    ctx.set_volume(vol.contiguous())
+    ctx.set_transfer_function(tf, w.extinction)
+    la = sg.lights_array(lights)
+    ctx.set_lights(la)
+    ctx.build_light_volume(0.5)
+    cam = wl.camera(w, 0, W, H)
+    G3 = (-0.75, 0.0, 0.75)
+    photons = 1 << args.st_photons
+    st = ctx.trace_photon_cache(photons, G3, cache_res=128, seed=21, max_collisions=8,
+                                rr_start=3)
+    ctx.field_select(0)
+    ctx.field_init(FieldConfig(), seed=21)
+    hist = ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, seed=21))
+    log(f"[st] trained on G = {G3}: {st['n_records']} records, loss {np.mean(hist[-20:]):.4g}")
+
+    def rc(g, indirect, spp=1, seed=3):
+        return RenderConfig(spp=spp, step_voxels=0.5, max_steps=1024, t_min=1e-3, field_stride=4,
+                            g=g, indirect=indirect, direct=DIRECT_LIGHT_VOLUME,
+                            field_precision="f16", field_slot=0, seed=seed)
+
+    def frame(cfg):
+        out = ctx.render_frame(cam, cfg)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+    def li_field(g):
+        return frame(rc(g, INDIRECT_FIELD)) - frame(rc(g, INDIRECT_NONE))
+
+    field_li = {g: li_field(g) for g in (-0.75, -0.35, 0.0, 0.35, 0.75)}
+    # the training trace's own cache, linear in g between its bins: the estimate without network
+    cache_li = {g: frame(rc(g, INDIRECT_CACHE)) - frame(rc(g, INDIRECT_NONE))
+                for g in (-0.75, -0.35, 0.0, 0.35, 0.75)}
+
+    def li_reference(g, seed):
+        ctx.trace_photon_cache(photons, (g,), cache_res=128, seed=seed, max_collisions=8,
+                               rr_start=3)
+        return frame(rc(g, INDIRECT_CACHE)) - frame(rc(g, INDIRECT_NONE))
+
+    phase = []
+    for i, g in enumerate((-0.75, -0.35, 0.0, 0.35, 0.75)):
+        ref = li_reference(g, 100 + i)
+        f, c = field_li[g], cache_li[g]
+        rel = lambda a: float(np.sqrt(np.mean((a - ref) ** 2)) / ref.mean())
+        phase.append({"g": g, "in_training_set": g in G3, "rel_rmse": rel(f), "ssim": ssim(f, ref),
+                      "cache_interp_rel_rmse": rel(c), "cache_interp_ssim": ssim(c, ref),
+                      "li_mean": float(ref.mean()), "field_li_mean": float(f.mean())})
+        log(f"[st] g={g:+.2f} ({'trained' if g in G3 else 'unseen '}): L_i rel-RMSE "
+            f"{phase[-1]['rel_rmse']:.4f}, SSIM {phase[-1]['ssim']:.4f} (field mean "
+            f"{f.mean():.4g} vs {ref.mean():.4g}); 3-bin cache in g: rel-RMSE {rel(c):.4f}, "
+            f"SSIM {phase[-1]['cache_interp_ssim']:.4f}")
+    a, b = li_reference(0.0, 300), li_reference(0.0, 301)
+    floor = {"rel_rmse": float(np.sqrt(np.mean((a - b) ** 2)) / b.mean()), "ssim": ssim(a, b)}
+    log(f"[st] two reference traces at g=0: rel-RMSE {floor['rel_rmse']:.4f}, "
+        f"SSIM {floor['ssim']:.4f}")
+
+    # noise: Algorithm 2 renderer with the field against the path tracer
+    g = 0.0
+    def fi(spp, seed):
+        out = ctx.render_first_interaction(cam, rc(g, INDIRECT_FIELD, spp=spp, seed=seed))
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+    def pt(spp, seed):
+        out = ctx.render_path_traced(cam, spp, max_bounces=16, g=g, seed=seed)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().astype(np.float64)
+
+    ref = pt(1024, 999)
+    noise = []
+    for spp in (1, 4, 8):
+        nf = float(np.sqrt(np.mean((fi(spp, 1) - fi(spp, 2)) ** 2) / 2) / ref.mean())
+        npt = float(np.sqrt(np.mean((pt(spp, 1) - pt(spp, 2)) ** 2) / 2) / ref.mean())
+        noise.append({"spp": spp, "field_first_interaction": nf, "path_tracer": npt})
+        log(f"[st] {spp} spp: relative noise field {nf:.4f}, path tracer {npt:.4f}")
+    ctx.close()
+    return {"metric": "phase-function awareness and stochastic noise", "value": None,
+            "unit": None, "n_gpus": 1, "data": "synthetic",
+            "config": {"workload": f"{w.name} at {W}x{H}", "training_bins": list(G3),
+                       "photons_per_trace": photons, "train_steps": args.train_steps},
+            "phase_awareness": phase, "tracing_floor_g0": floor, "noise": noise}
 
 
 def cpu_baseline(args, w, vol, tf, la, ctx, cam, fcfg, rc):
