@@ -736,12 +736,53 @@ def studies(args):
         npt = float(np.sqrt(np.mean((pt(spp, 1) - pt(spp, 2)) ** 2) / 2) / ref.mean())
         noise.append({"spp": spp, "field_first_interaction": nf, "path_tracer": npt})
         log(f"[st] {spp} spp: relative noise field {nf:.4f}, path tracer {npt:.4f}")
+    # the configuration against the paper's network settings (but for its 8 features per level):
+    # 5 hidden layers, level growth 2 (12 levels, so that the finest stays within the 2^16 grid
+    # coordinates of the encoding), batches of 2^16, relative L2; trained on one 5-phase trace
+    # and judged on L_i against single-phase reference traces
+    st5 = ctx.trace_photon_cache(photons, wl.C1_G_BINS, cache_res=128, seed=31, max_collisions=8,
+                                 rr_start=3)
+    variants = {
+        "configuration": (FieldConfig(), TrainConfig(steps=args.train_steps, log2_batch=18,
+                                                     seed=31)),
+        "paper_network_rel_l2": (FieldConfig(hidden_layers=5, growth=2.0, levels=12),
+                                 TrainConfig(steps=args.train_steps, log2_batch=16, seed=31,
+                                             loss="rel")),
+        "paper_network_l2": (FieldConfig(hidden_layers=5, growth=2.0, levels=12),
+                             TrainConfig(steps=args.train_steps, log2_batch=16, seed=31)),
+    }
+    ab = {}
+    for slot, (name, (fc, tc)) in enumerate(variants.items()):
+        ctx.field_select(1 + slot)
+        ctx.field_init(fc, seed=31)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        hist = ctx.train_field(tc)
+        torch.cuda.synchronize()
+        ab[name] = {"hidden_layers": fc.hidden_layers, "growth": fc.growth,
+                    "batch": 1 << tc.log2_batch, "loss": tc.loss,
+                    "train_s": round(time.perf_counter() - ts, 3),
+                    "final_loss": float(np.mean(hist[-20:])), "per_g": {}}
+    for i, g in enumerate((0.4, 0.2)):
+        ref = li_reference(g, 400 + i)
+        for slot, name in enumerate(variants):
+            cfg = rc(g, INDIRECT_FIELD)
+            cfg.field_slot = 1 + slot
+            f = frame(cfg) - frame(rc(g, INDIRECT_NONE))
+            ab[name]["per_g"][str(g)] = {
+                "rel_rmse": float(np.sqrt(np.mean((f - ref) ** 2)) / ref.mean()),
+                "ssim": ssim(f, ref)}
+            log(f"[st] {name} g={g}: L_i rel-RMSE {ab[name]['per_g'][str(g)]['rel_rmse']:.4f}, "
+                f"SSIM {ab[name]['per_g'][str(g)]['ssim']:.4f}, train {ab[name]['train_s']} s")
+    ctx.field_select(0)
     ctx.close()
     return {"metric": "phase-function awareness and stochastic noise", "value": None,
             "unit": None, "n_gpus": 1, "data": "synthetic",
             "config": {"workload": f"{w.name} at {W}x{H}", "training_bins": list(G3),
                        "photons_per_trace": photons, "train_steps": args.train_steps},
-            "phase_awareness": phase, "tracing_floor_g0": floor, "noise": noise}
+            "phase_awareness": phase, "tracing_floor_g0": floor, "noise": noise,
+            "network_settings": {"trace": f"{st5['n_records']} records, bins {list(wl.C1_G_BINS)}",
+                                 "variants": ab}}
 
 
 def cpu_baseline(args, w, vol, tf, la, ctx, cam, fcfg, rc):

@@ -178,12 +178,14 @@ pfn_status pfn_field_set_kappa(pfn_context *ctx, double kappa);
 pfn_status pfn_field_query(pfn_context *ctx, pfn_dtype precision, const float *dev_xyz,
                            const float *dev_dir, const float *dev_g, int64_t n,
                            float *dev_lprime, float *dev_rgb);
-/* L2 loss mean((L' - target)^2) over n x 3 outputs and its gradient with respect to every
- * parameter (same layout as the parameter vector), FP32 accumulation.  Synchronises. */
+/* Loss over n x 3 outputs and its gradient with respect to every parameter (same layout as the
+ * parameter vector), FP32 accumulation.  loss_mode 0: L2, mean((L' - target)^2); 1: relative L2
+ * (Section 3.5.1), mean((L' - target)^2 / (L'^2 + 0.01)) with the denominator held constant in
+ * the gradient.  Synchronises. */
 pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype precision, const float *dev_xyz,
                                       const float *dev_dir, const float *dev_g,
-                                      const float *dev_target, int64_t n, double *host_loss,
-                                      float *dev_grad);
+                                      const float *dev_target, int64_t n, int loss_mode,
+                                      double *host_loss, float *dev_grad);
 
 typedef struct {
   int steps;            /* training steps */
@@ -197,6 +199,7 @@ typedef struct {
   int knn_k;            /* photon-map targets: K nearest (0: every record within the radius) */
   float radius;         /* photon-map targets: the final (maximum) query radius, cube units */
   int staggered;        /* photon-map targets: 1 = the staggered schedule of Section 3.5.2 */
+  int loss;             /* 0: L2 (the configuration); 1: relative L2 (Section 3.5.1) */
 } pfn_train_params;
 
 /* Section 3.5: each step draws a fresh batch (uniform x, uniform direction, g from the cache

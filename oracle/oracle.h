@@ -95,6 +95,11 @@ void orc_field_forward(const orc_field_desc *d, const double *params, int roundi
 double orc_field_loss_grad(const orc_field_desc *d, const double *params, int rounding, int64_t n,
                            const double *xyz, const double *dir, const double *g,
                            const double *target, double *grad /* n_params, overwritten */);
+/* The same with a choice of loss: 0 = L2, 1 = relative L2 (y - t)^2 / (y^2 + 0.01) per output,
+ * the denominator held constant in the gradient. */
+double orc_field_loss_grad_mode(const orc_field_desc *d, const double *params, int rounding,
+                                int loss_mode, int64_t n, const double *xyz, const double *dir,
+                                const double *g, const double *target, double *grad);
 /* Encoding of one input: z has layout.n_in entries. */
 void orc_field_encode(const orc_field_desc *d, const double *params, int rounding, const double x[3],
                       const double w[3], double g, double *z);

@@ -262,9 +262,12 @@ void orc_field_forward(const orc_field_desc *d, const double *params, int roundi
 /* L2 loss mean over samples and the three channels; analytic gradient with respect to every
  * parameter (grid tables and weight matrices).  When the parameters are rounded before use, the
  * gradient is taken with the rounded values (the update applies to the unrounded master). */
-double orc_field_loss_grad(const orc_field_desc *d, const double *params, int rounding, int64_t n,
-                           const double *xyz, const double *dir, const double *g,
-                           const double *target, double *grad) {
+/* loss 0: L2, sum (y - t)^2; loss 1: relative L2, sum (y - t)^2 / (y^2 + 0.01) with the
+ * denominator held constant in the gradient (the relative MSE of Section 3.5.1 in the form of
+ * the network library the paper trains with). */
+double orc_field_loss_grad_mode(const orc_field_desc *d, const double *params, int rounding,
+                                int loss_mode, int64_t n, const double *xyz, const double *dir,
+                                const double *g, const double *target, double *grad) {
   orc_field_layout L;
   orc_field_make_layout(d, &L);
   memset(grad, 0, L.n_params * sizeof(double));
@@ -287,8 +290,9 @@ double orc_field_loss_grad(const orc_field_desc *d, const double *params, int ro
       mlp_forward(&L, params, rounding, z, st, y);
       for (int c = 0; c < 3; ++c) {
         double e = y[c] - target[3 * i + c];
-        loss += e * e;
-        delta[c] = scale * e;
+        double w = loss_mode == 1 ? 1.0 / (y[c] * y[c] + 0.01) : 1.0;
+        loss += e * e * w;
+        delta[c] = scale * e * w;
       }
       for (int m = L.n_mats - 1; m >= 0; --m) {
         const double *W = params + L.w_off[m];
@@ -383,4 +387,10 @@ void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *ca
     orc_cache_gather_bin(cache, b, x, v);
     for (int c = 0; c < 3; ++c) target[3 * i + c] = orc_log_encode(v[c] / kappa, psi);
   }
+}
+
+double orc_field_loss_grad(const orc_field_desc *d, const double *params, int rounding, int64_t n,
+                           const double *xyz, const double *dir, const double *g,
+                           const double *target, double *grad) {
+  return orc_field_loss_grad_mode(d, params, rounding, 0, n, xyz, dir, g, target, grad);
 }

@@ -128,6 +128,9 @@ def lib():
         L.orc_field_loss_grad.restype = C.c_double
         L.orc_field_loss_grad.argtypes = [C.POINTER(FieldDesc), dp, C.c_int, C.c_int64, dp, dp,
                                           dp, dp, dp]
+        L.orc_field_loss_grad_mode.restype = C.c_double
+        L.orc_field_loss_grad_mode.argtypes = [C.POINTER(FieldDesc), dp, C.c_int, C.c_int,
+                                               C.c_int64, dp, dp, dp, dp, dp]
         L.orc_field_encode.argtypes = [C.POINTER(FieldDesc), dp, C.c_int, dp, dp, C.c_double, dp]
         L.orc_round_half.restype = C.c_double
         L.orc_round_half.argtypes = [C.c_double]
@@ -303,14 +306,18 @@ def field_forward(desc, params, xyz, dirs, g, rounding=0) -> np.ndarray:
     return out
 
 
-def field_loss_grad(desc, params, xyz, dirs, g, target, rounding=0):
+def field_loss_grad(desc, params, xyz, dirs, g, target, rounding=0, loss="l2"):
+    """Mean of the loss over n x 3 outputs and its gradient; loss "l2" or
+    "rel" (relative L2, denominator held constant in the gradient)."""
     params = _d(params)
     xyz, dirs, g = _d(xyz).reshape(-1, 3), _d(dirs).reshape(-1, 3), _d(g).reshape(-1)
     target = _d(target).reshape(-1, 3)
     grad = np.zeros(params.size)
-    loss = lib().orc_field_loss_grad(C.byref(desc), _ptr(params), rounding, xyz.shape[0],
-                                     _ptr(xyz), _ptr(dirs), _ptr(g), _ptr(target), _ptr(grad))
-    return loss, grad
+    mode = {"l2": 0, "rel": 1}[loss]
+    val = lib().orc_field_loss_grad_mode(C.byref(desc), _ptr(params), rounding, mode,
+                                         xyz.shape[0], _ptr(xyz), _ptr(dirs), _ptr(g),
+                                         _ptr(target), _ptr(grad))
+    return val, grad
 
 
 def field_encode(desc, params, x, w, g, rounding=0) -> np.ndarray:

@@ -49,7 +49,8 @@ class TrainParams(C.Structure):
                 ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
                 ("decay", C.c_float), ("decay_start", C.c_int), ("decay_interval", C.c_int),
                 ("precision", C.c_int), ("seed", C.c_uint64), ("target", C.c_int),
-                ("knn_k", C.c_int), ("radius", C.c_float), ("staggered", C.c_int)]
+                ("knn_k", C.c_int), ("radius", C.c_float), ("staggered", C.c_int),
+                ("loss", C.c_int)]
 
 
 class CameraS(C.Structure):
@@ -93,7 +94,7 @@ SIGNATURES = {
     "pfn_field_set_params": (C.c_int, [ctxp, vp, C.c_size_t]),
     "pfn_field_set_kappa": (C.c_int, [ctxp, C.c_double]),
     "pfn_field_query": (C.c_int, [ctxp, C.c_int, vp, vp, vp, C.c_int64, vp, vp]),
-    "pfn_field_forward_backward": (C.c_int, [ctxp, C.c_int, vp, vp, vp, vp, C.c_int64,
+    "pfn_field_forward_backward": (C.c_int, [ctxp, C.c_int, vp, vp, vp, vp, C.c_int64, C.c_int,
                                              C.POINTER(C.c_double), vp]),
     "pfn_train_field": (C.c_int, [ctxp, C.POINTER(TrainParams), C.POINTER(C.c_float)]),
     "pfn_train_batch": (C.c_int, [ctxp, C.c_uint64, C.c_int64, C.c_int64, vp, vp, vp, vp, vp]),

@@ -206,7 +206,8 @@ struct TrainArgs {
   float *grad_pos, *grad_dir;  // FP32 gradients of the grid tables (2 floats per entry)
   void *act;        // per-layer deltas and inputs, neuron-major [rows][ldn]
   int64_t delta_off[PFN_MAX_HIDDEN + 1], in_off[PFN_MAX_HIDDEN + 1];  // element offsets
-  double *loss;     // accumulated sum of squared residuals
+  double *loss;     // accumulated sum of (weighted) squared residuals
+  int rel_loss;     // 1: relative L2, residuals weighted by 1 / (y^2 + 0.01) (held constant)
 };
 
 template <typename T>
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
       if (q == 0) in0[(int64_t)(4 * L) * a.ldn + i] = to_t<T>(valid ? g : 0.f);
     }
 
-    float e[3];
+    float e[3], lsum[3];
     if constexpr (P == P_F32) {
       const float *W = reinterpret_cast<const float *>(a.fwd);
       const float *B = reinterpret_cast<const float *>(a.bwd);
@@ -379,7 +380,13 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
         for (int r = 0; r < 4; ++r)
           out = __builtin_amdgcn_mfma_f32_16x16x4f32(wl[(t * 4 + r) * 64 + lane], hv[H - 1][t][r], out, 0, 0, 0);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) e[c] = valid ? (__shfl(out[c], nl) - tgt[c]) : 0.0f;
+      for (int c = 0; c < 3; ++c) {
+        const float y = __shfl(out[c], nl);
+        const float r = valid ? y - tgt[c] : 0.0f;
+        const float wgt = a.rel_loss ? 1.0f / fmaf(y, y, 0.01f) : 1.0f;
+        e[c] = r * wgt;
+        lsum[c] = r * r * wgt;
+      }
       // output layer: delta = e (rows = channels), input = h_{H-1}
       if (q == 0) {
         T *d = act + a.delta_off[H];
@@ -483,7 +490,13 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
       out = M::mma(wl[0 * 64 + lane], hv[H - 1][0], out);
       out = M::mma(wl[1 * 64 + lane], hv[H - 1][1], out);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) e[c] = valid ? (__shfl(out[c], nl) - tgt[c]) : 0.0f;
+      for (int c = 0; c < 3; ++c) {
+        const float y = __shfl(out[c], nl);
+        const float r = valid ? y - tgt[c] : 0.0f;
+        const float wgt = a.rel_loss ? 1.0f / fmaf(y, y, 0.01f) : 1.0f;
+        e[c] = r * wgt;
+        lsum[c] = r * r * wgt;
+      }
       if (q == 0) {
         T *d = act + a.delta_off[H];
 #pragma unroll
@@ -543,7 +556,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
         scatter_grid_grads(a, q, x, u0, u1, gp, gd);
       }
     }
-    if (q == 0) wave_loss += (double)(e[0] * e[0]) + (double)(e[1] * e[1]) + (double)(e[2] * e[2]);
+    if (q == 0) wave_loss += (double)lsum[0] + (double)lsum[1] + (double)lsum[2];
   }
   for (int off = 32; off > 0; off >>= 1) wave_loss += __shfl_down(wave_loss, off);
   if (lane == 0 && wave_loss != 0.0) atomicAdd(a.loss, wave_loss);
@@ -702,6 +715,8 @@ static hipError_t launch_fb_h(const TrainArgs &a, int H, unsigned blocks, hipStr
     case 1: return launch_fb_t<P, 1, GEN>(a, blocks, st);
     case 2: return launch_fb_t<P, 2, GEN>(a, blocks, st);
     case 3: return launch_fb_t<P, 3, GEN>(a, blocks, st);
+    case 4: return launch_fb_t<P, 4, GEN>(a, blocks, st);
+    case 5: return launch_fb_t<P, 5, GEN>(a, blocks, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -715,7 +730,7 @@ static hipError_t launch_fb(const TrainArgs &a, int prec, int H, unsigned blocks
 // Forward/backward over n samples into f.grad (unscaled), loss sum into *loss_dev.
 static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bool gen,
                          const SampleSrc &src, const float *xyz, const float *dir, const float *g,
-                         const float *tgt, double *loss_dev) {
+                         const float *tgt, double *loss_dev, int rel_loss) {
   const int H = f.desc.hidden_layers;
   TrainLayout tl = train_layout(H, n);
   TrainArgs a{};
@@ -737,6 +752,7 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
     a.in_off[m] = tl.in_off[m];
   }
   a.loss = loss_dev;
+  a.rel_loss = rel_loss;
   int64_t ntiles = tl.ldn / 16;
   unsigned blocks = (unsigned)((ntiles + 3) / 4);
   const int tslot = timing_begin(ctx);
@@ -801,8 +817,8 @@ static pfn_status run_adam(pfn_context *ctx, FieldSlot &f, float *grad, int64_t 
 
 static pfn_status check_training_field(pfn_context *ctx, FieldSlot &f) {
   if (!f.init) return pfn_fail(ctx, PFN_ERR_NOT_READY, "field not initialised");
-  if (f.desc.hidden_layers > 3)
-    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training supports 1 to 3 hidden layers");
+  if (f.desc.hidden_layers > 5)
+    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "training supports 1 to 5 hidden layers");
   return PFN_OK;
 }
 
@@ -841,12 +857,15 @@ extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t s
 extern "C" pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype precision,
                                                  const float *xyz, const float *dir,
                                                  const float *g, const float *tgt, int64_t n,
-                                                 double *host_loss, float *dev_grad) {
+                                                 int loss_mode, double *host_loss,
+                                                 float *dev_grad) {
   if (!ctx) return PFN_ERR_INVALID_ARG;
   if (!(precision == PFN_F32 || precision == PFN_F16 || precision == PFN_BF16))
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad precision");
   if (n < 1 || n > ((int64_t)1 << 26)) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "n in [1, 2^26]");
   if (!xyz || !dir || !g || !tgt) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "NULL input");
+  if (loss_mode != 0 && loss_mode != 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "loss: 0 (L2) or 1 (relative L2)");
   FieldSlot &f = ctx->fields[ctx->cur_field];
   pfn_status st = check_training_field(ctx, f);
   if (st) return st;
@@ -862,7 +881,7 @@ extern "C" pfn_status pfn_field_forward_backward(pfn_context *ctx, pfn_dtype pre
   PFN_HIP(ctx, hipMemsetAsync(loss_dev, 0, sizeof(double), ctx->stream));
   PFN_HIP(ctx, hipMemsetAsync(f.grad, 0, f.n_params * 4, ctx->stream));
   SampleSrc src{};
-  st = run_fb(ctx, f, prec, n, false, src, xyz, dir, g, tgt, loss_dev);
+  st = run_fb(ctx, f, prec, n, false, src, xyz, dir, g, tgt, loss_dev, loss_mode);
   if (st) return st;
   const float scale = (float)(2.0 / (3.0 * (double)n));
   if (dev_grad) {
@@ -933,6 +952,8 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
   if (!ctx->cache_valid) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no photon cache");
   if (p->target != 0 && p->target != 1)
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "target: 0 (cache) or 1 (photon map)");
+  if (p->loss != 0 && p->loss != 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "loss: 0 (L2) or 1 (relative L2)");
   const bool map_targets = p->target == 1;
   if (map_targets) {
     if (!(std::isfinite(p->radius) && p->radius > 0.0f && p->radius <= 2.0f))
@@ -988,9 +1009,10 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
       hipLaunchKernelGGL(log_target_kernel, dim3((unsigned)((3 * n + 255) / 256)), dim3(256), 0,
                          ctx->stream, b_val, b_tgt, 3 * n, src.inv_kappa, src.psi);
       PFN_HIP(ctx, hipGetLastError());
-      st = run_fb(ctx, f, prec, n, false, src, b_xyz, b_dir, b_g, b_tgt, loss_dev + s);
+      st = run_fb(ctx, f, prec, n, false, src, b_xyz, b_dir, b_g, b_tgt, loss_dev + s, p->loss);
     } else {
-      st = run_fb(ctx, f, prec, n, true, src, nullptr, nullptr, nullptr, nullptr, loss_dev + s);
+      st = run_fb(ctx, f, prec, n, true, src, nullptr, nullptr, nullptr, nullptr, loss_dev + s,
+                  p->loss);
     }
     if (st) return st;
     double lr = p->lr;

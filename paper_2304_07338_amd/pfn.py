@@ -64,6 +64,9 @@ class RenderConfig:
                                  self.field_slot, self.seed)
 
 
+LOSSES = {"l2": 0, "rel": 1}
+
+
 @dataclasses.dataclass
 class TrainConfig:
     steps: int = 2000
@@ -81,13 +84,14 @@ class TrainConfig:
     knn_k: int = 0
     radius: float = 0.05
     staggered: bool = False
+    loss: str = "l2"        # or "rel" (relative L2 of Section 3.5.1)
 
     def struct(self) -> _ffi.TrainParams:
         return _ffi.TrainParams(self.steps, self.log2_batch, self.lr, self.beta1, self.beta2,
                                 self.eps, self.decay, self.decay_start, self.decay_interval,
                                 DTYPES[self.precision], self.seed,
                                 {"cache": 0, "photon_map": 1}[self.target], self.knn_k,
-                                self.radius, int(self.staggered))
+                                self.radius, int(self.staggered), LOSSES[self.loss])
 
 
 def train_step_radius(cfg: "TrainConfig", step: int) -> float:
@@ -330,15 +334,17 @@ class Context:
                                           _ptr(g), n, _ptr(lp), _ptr(rgb)))
         return (lp, rgb) if decode else lp
 
-    def field_forward_backward(self, xyz, dirs, g, target, precision: str = "f32"):
+    def field_forward_backward(self, xyz, dirs, g, target, precision: str = "f32",
+                               loss: str = "l2"):
+        """Loss ("l2" or "rel": relative L2) over n x 3 outputs and its parameter gradient."""
         import torch
         n = xyz.shape[0]
         grad = torch.empty(self.field_num_params(), dtype=torch.float32, device=xyz.device)
-        loss = C.c_double()
+        val = C.c_double()
         self._ok(self.lib.pfn_field_forward_backward(self.h, DTYPES[precision], _ptr(xyz),
                                                      _ptr(dirs), _ptr(g), _ptr(target), n,
-                                                     C.byref(loss), _ptr(grad)))
-        return loss.value, grad
+                                                     LOSSES[loss], C.byref(val), _ptr(grad)))
+        return val.value, grad
 
     def train_field(self, cfg: TrainConfig = TrainConfig(), history: bool = True):
         hist = np.zeros(cfg.steps, dtype=np.float32) if history else None

@@ -175,6 +175,39 @@ def test_loss_gradient_matches_finite_differences(orc):
         assert fd == pytest.approx(grad[j], rel=1e-5, abs=1e-9), j
 
 
+def test_relative_loss_gradient_is_the_weighted_l2_gradient(orc):
+    """Relative L2: sum (y - t)^2 / (y^2 + 0.01) with the denominator held constant, i.e. the
+    gradient of sum w (y - t)^2 with w frozen at the current prediction (checked by central
+    differences of that frozen-weight loss), and the loss value at the current parameters."""
+    d = small_desc(orc, levels=5, base_res=3, log2_table=7, hidden_layers=2, width=8)
+    L = orc.field_layout(d)
+    rng = np.random.default_rng(18)
+    p = rng.normal(scale=0.3, size=L.n_params)
+    n = 16
+    xs = rng.uniform(size=(n, 3))
+    ws = rng.normal(size=(n, 3))
+    ws /= np.linalg.norm(ws, axis=1, keepdims=True)
+    gs = rng.uniform(-0.8, 0.8, n)
+    tgt = rng.uniform(size=(n, 3))
+    loss, grad = orc.field_loss_grad(d, p, xs, ws, gs, tgt, loss="rel")
+    out = orc.field_forward(d, p, xs, ws, gs)
+    wfz = 1.0 / (out ** 2 + 0.01)
+    assert loss == pytest.approx(np.mean((out - tgt) ** 2 * wfz), rel=1e-12)
+    l2, g2 = orc.field_loss_grad(d, p, xs, ws, gs, tgt)
+    assert not np.allclose(grad, g2)  # the weighting changes the gradient
+    idx = np.concatenate([np.flatnonzero(grad)[:: max(1, np.count_nonzero(grad) // 100)],
+                          rng.integers(0, L.n_params, 10)])
+    h = 1e-6
+    for j in idx:
+        pp = p.copy()
+        pp[j] += h
+        lp = np.mean(wfz * (orc.field_forward(d, pp, xs, ws, gs) - tgt) ** 2)
+        pp[j] -= 2 * h
+        lm = np.mean(wfz * (orc.field_forward(d, pp, xs, ws, gs) - tgt) ** 2)
+        fd = (lp - lm) / (2 * h)
+        assert fd == pytest.approx(grad[j], rel=5e-5, abs=1e-8), j  # weights up to 100
+
+
 def test_rounding_matches_library_conversions(orc):
     rng = np.random.default_rng(9)
     vals = np.concatenate([rng.normal(scale=s, size=2000) for s in (1e-6, 1e-3, 1.0, 300.0)])
