@@ -149,18 +149,34 @@ struct PmWaveLds {
   uint32_t n_buf;
 };
 
+// Distance from v to the cell interval [c / G, (c + 1) / G] along one axis (0 inside).
+__device__ __forceinline__ float pm_gap(float v, int c, float inv_g) {
+  const float lo = (float)c * inv_g, hi = (float)(c + 1) * inv_g;
+  return fmaxf(fmaxf(lo - v, v - hi), 0.0f);
+}
+
 // Visits the records of bin b in the cells that the sphere of radius R around x touches:
-// f(d2, record) per record, the wave's lanes taking 64 consecutive records at a time.
+// f(d2, record) per record, the wave's lanes taking 64 consecutive records at a time.  A
+// (z, y) row of cells is skipped when its nearest point is farther than R, and within a row
+// only the cells under the sphere's chord are read.  Both tests use R (1 + 1e-5) + 1e-6, a
+// margin above the FP32 rounding of cell bounds and coordinates (a few 1e-7), so that no record
+// that the FP32 test d2 <= R^2 accepts is missed.
 template <typename F>
 __device__ __forceinline__ void pm_for_candidates(const PmEstArgs &a, int b, f3 x, F &&f) {
   const int G = a.G;
-  const float R = a.radius;
-  const int x0 = pm_cell(x.x - R, G), x1 = pm_cell(x.x + R, G);
-  const int y0 = pm_cell(x.y - R, G), y1 = pm_cell(x.y + R, G);
-  const int z0 = pm_cell(x.z - R, G), z1 = pm_cell(x.z + R, G);
+  const float R = a.radius, Rm = R * (1.0f + 1e-5f) + 1e-6f, R2m = Rm * Rm;
+  const float inv_g = 1.0f / (float)G;
+  const int y0 = pm_cell(x.y - Rm, G), y1 = pm_cell(x.y + Rm, G);
+  const int z0 = pm_cell(x.z - Rm, G), z1 = pm_cell(x.z + Rm, G);
   const uint32_t lane = (uint32_t)lane_id();
-  for (int cz = z0; cz <= z1; ++cz)
+  for (int cz = z0; cz <= z1; ++cz) {
+    const float gz = pm_gap(x.z, cz, inv_g);
     for (int cy = y0; cy <= y1; ++cy) {
+      const float gy = pm_gap(x.y, cy, inv_g);
+      const float rest = R2m - gz * gz - gy * gy;
+      if (rest < 0.0f) continue;
+      const float half = sqrtf(rest) * (1.0f + 1e-5f) + 1e-6f;
+      const int x0 = pm_cell(x.x - half, G), x1 = pm_cell(x.x + half, G);
       const int64_t row = (((int64_t)b * G + cz) * G + cy) * G;
       const uint32_t s0 = a.start[row + x0], s1 = a.start[row + x1 + 1];
       for (uint32_t j = s0 + lane; j < s1; j += 64) {
@@ -169,6 +185,7 @@ __device__ __forceinline__ void pm_for_candidates(const PmEstArgs &a, int b, f3 
         f(dx * dx + dy * dy + dz * dz, j);
       }
     }
+  }
 }
 
 __device__ __forceinline__ float pm_wave_sum(float v) {
