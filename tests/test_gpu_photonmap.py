@@ -243,3 +243,41 @@ def test_training_on_photon_map_targets_converges():
     say(f"  photon-map targets, 300 steps: loss {hist[:10].mean():.4g} -> {hist[-10:].mean():.4g}")
     assert hist[-10:].mean() < 0.3 * hist[:10].mean()
     ctx.close()
+
+
+def test_invalid_photon_map_calls_are_rejected():
+    import torch
+    from paper_2304_07338_amd import workloads as wl
+    from paper_2304_07338_amd.pfn import FieldConfig, PfnError, TrainConfig
+    w, vol, tf, lights = scene_arrays("c0")
+    ctx = gpu_context(vol, tf, lights)
+    q = torch.zeros((4, 3), dtype=torch.float32, device="cuda:0") + 0.5
+    d = torch.tensor([[0.0, 0.0, 1.0]] * 4, dtype=torch.float32, device="cuda:0")
+    b = torch.zeros(4, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(PfnError):  # no map yet
+        ctx.photon_map_estimate(q, d, b, 0.1, 8)
+    with pytest.raises(PfnError):  # no trace yet
+        ctx.photon_map_build(16)
+    st = ctx.trace_photon_cache(1 << 16, wl.C1_G_BINS, cache_res=16, seed=1)
+    with pytest.raises(PfnError):
+        ctx.photon_map_build(0)
+    with pytest.raises(PfnError):
+        ctx.photon_map_build(129)
+    ctx.photon_map_build(16)
+    for radius, k in ((0.0, 8), (-0.1, 0), (2.5, 0), (0.1, -1)):
+        with pytest.raises(PfnError):
+            ctx.photon_map_estimate(q, d, b, radius, k)
+    rgb, r, cnt = ctx.photon_map_estimate(q, d, b, 0.2, 8)
+    assert torch.isfinite(rgb).all() and int(cnt.min()) >= 0
+    # a map whose bins differ from the cache's cannot train the field
+    x = torch.rand((100, 3), device="cuda:0")
+    ctx.photon_map_set(x, d[:1].repeat(100, 1).contiguous(), torch.ones_like(x),
+                       torch.zeros(100, dtype=torch.int32, device="cuda:0"), [0.0], grid_res=8)
+    ctx.field_select(0)
+    ctx.field_init(FieldConfig(log2_table=12), seed=1)
+    with pytest.raises(PfnError):
+        ctx.train_field(TrainConfig(steps=2, log2_batch=8, target="photon_map", radius=0.1))
+    with pytest.raises(PfnError):
+        ctx.photon_map_set(x, x, x, torch.zeros(100, dtype=torch.int32, device="cuda:0"),
+                           [0.99], grid_res=8)
+    ctx.close()
