@@ -202,10 +202,11 @@ def main():
     kernels = {}
     if ktimes["wf_march_kernel"][1] > 0:
         # wavefront form: per kernel, per frame
-        n_groups = 1 + 7  # coarse levels together, then each fine hashed level (C1 field)
+        # the position encoding reads a query's 16 x 8 grid corners and its position once and
+        # writes its 16 features (the launches that read the position again, and the direction
+        # launches timed with them, add no algorithmic bytes)
         per = {"wf_march_kernel": (steps_f * step_bytes + queries_f * 24, 0),
-               "wf_encode_kernel": (queries_f * (16 * 8 * feat_bytes + 16 * feat_bytes
-                                                 + 12 * n_groups), 0),
+               "wf_encode_kernel": (queries_f * (16 * 8 * feat_bytes + 16 * feat_bytes + 12), 0),
                "wf_field_kernel": (queries_f * (16 * feat_bytes + 12), queries_f * mlp_flop),
                "wf_resolve_kernel": (0, 0)}
         for k, (ms, n) in ktimes.items():

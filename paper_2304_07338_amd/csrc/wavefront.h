@@ -38,6 +38,8 @@ struct WfEncArgs {
   int l0, l1;
   int per_level;        // 0: a thread encodes levels l0..l1-1 of its query; > 0: a thread
                         // encodes one level, per_level threads per level, level-major
+  int xcd_levels;       // 2 or 4: levels l0 .. l0 + xcd_levels - 1, each on its own 8 /
+                        // xcd_levels XCDs, so that each XCD's L2 holds one level's table
 };
 
 struct WfDirArgs {

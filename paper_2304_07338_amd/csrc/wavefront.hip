@@ -24,6 +24,10 @@
 // renders exactly as its jobs rendered alone.
 #include "wavefront.h"
 
+#ifndef WF_XCD_LEVELS
+#define WF_XCD_LEVELS 2  // fine levels per encoding launch, each on 8 / WF_XCD_LEVELS XCDs
+#endif
+
 struct WfList {
   uint32_t *ray;
   int *j;
@@ -246,7 +250,14 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   // with per_level, one level of it)
   int64_t g = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
   int l0 = e.l0, l1 = e.l1;
-  if (e.per_level) {
+  if (e.xcd_levels) {
+    // workgroups go to the XCDs round-robin: blockIdx % 8 is the XCD; level l0 + j runs on the
+    // per = 8 / xcd_levels XCDs j * per .. j * per + per - 1
+    const int xcd = (int)(blockIdx.x & 7), per = 8 / e.xcd_levels;
+    l0 += xcd / per;
+    l1 = l0 + 1;
+    g = ((int64_t)(blockIdx.x >> 3) * per + (xcd % per)) * WF_THREADS + threadIdx.x;
+  } else if (e.per_level) {
     const int dl = (int)(g / e.per_level);
     g -= (int64_t)dl * e.per_level;
     l0 += dl;
@@ -549,9 +560,16 @@ static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, con
     WfEncArgs ee = e;
     ee.l0 = g.first;
     ee.l1 = g.second;
-    ee.per_level = split_levels && g.second - g.first > 1 ? (int)threads : 0;
+    // fine levels spread over the XCDs are marked by a negative end: -(level count)
+    ee.xcd_levels = g.second < 0 ? -g.second : 0;
+    if (ee.xcd_levels) ee.l1 = g.first + ee.xcd_levels;
+    ee.per_level = !ee.xcd_levels && split_levels && g.second - g.first > 1 ? (int)threads : 0;
     const int64_t n = ee.per_level ? threads * (g.second - g.first) : threads;
-    const int eb = (int)((n + WF_THREADS - 1) / WF_THREADS);
+    int eb = (int)((n + WF_THREADS - 1) / WF_THREADS);
+    if (ee.xcd_levels) {
+      const int per = 8 / ee.xcd_levels;
+      eb = 8 * ((eb + per - 1) / per);
+    }
     const int ts = timing_begin_on(ctx, st);
     hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
     timing_end_on(ctx, ts, TK_WF_ENCODE, st);
@@ -663,7 +681,31 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
                               hipMemcpyHostToDevice, ctx->stream));
   PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
 
-  const std::vector<std::pair<int, int>> groups = wf_level_groups(ctx, slot, fd_host, fbytes);
+  std::vector<std::pair<int, int>> groups;
+  {
+    // runs of single fine levels go WF_XCD_LEVELS (then 2) at a time, each level on its own
+    // share of the XCDs; marked by the end -(level count)
+    const std::vector<std::pair<int, int>> g0 = wf_level_groups(ctx, slot, fd_host, fbytes);
+    auto fine_single = [&](size_t i) {
+      return g0[i].second == g0[i].first + 1 &&
+             (fd_host.pos.dense_mask >> g0[i].first & 1u) == 0 &&
+             fd_host.pos.res[g0[i].first] >= WF_FINE_RES;
+    };
+    for (size_t i = 0; i < g0.size();) {
+      size_t run = 0;
+      while (i + run < g0.size() && fine_single(i + run)) ++run;
+      if (run == 0) {
+        groups.push_back(g0[i++]);
+        continue;
+      }
+      while (run > 0) {
+        const int take = run >= WF_XCD_LEVELS ? WF_XCD_LEVELS : run >= 2 ? 2 : 1;
+        groups.push_back(take == 1 ? g0[i] : std::make_pair(g0[i].first, -take));
+        i += take;
+        run -= take;
+      }
+    }
+  }
   const int fb_max = wf_field_blocks(prec, m.mlp_bytes);
   hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream;
 
