@@ -215,7 +215,9 @@ typedef struct {
  * Synchronises. */
 pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *params,
                            float *host_loss_history);
-/* The photon-map query radius that pfn_train_field uses at `step` (host only, no context). */
+/* The photon-map query radius that pfn_train_field uses at `step` (the staggered schedule of
+ * Section 3.5.2 and Table 1, or the final radius); host only, no context, no GPU.  Returns
+ * PFN_ERR_INVALID_ARG for NULL pointers, steps < 1 or step outside [0, steps). */
 pfn_status pfn_train_step_radius(const pfn_train_params *params, int step, float *host_radius);
 /* The training-batch generator alone (for checking): step `step`'s n samples. */
 pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
