@@ -1001,6 +1001,20 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
   TileConfig best{};
   double best_ms = -1.0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // on every exit (errors included): the caller's launch settings back, the events freed
+  struct Restore {
+    pfn_context *c;
+    bool graph, timing;
+    int strategy;
+    hipEvent_t *a, *b;
+    ~Restore() {
+      c->use_graph = graph;
+      c->timing = timing;
+      c->strategy = strategy;
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } restore{ctx, saved_graph, saved_timing, saved_strategy, &e0, &e1};
   for (int form : forms) {
     std::vector<unsigned char> key = base;
     const int graph = form == PFN_STRATEGY_FUSED && saved_graph;
@@ -1072,11 +1086,9 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
       best = fbest;
     }
   }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
   if (st) return st;
   ctx->tile = best;
-  ctx->strategy = best.strategy;
+  restore.strategy = best.strategy;  // the chosen form becomes the context's (on return)
   if (out_strategy) *out_strategy = best.strategy;
   if (out_tile_w) *out_tile_w = best.tile_w;
   if (out_block_w) *out_block_w = best.block_w;
