@@ -179,10 +179,20 @@ __device__ __forceinline__ void pm_for_candidates(const PmEstArgs &a, int b, f3 
       const int x0 = pm_cell(x.x - half, G), x1 = pm_cell(x.x + half, G);
       const int64_t row = (((int64_t)b * G + cz) * G + cy) * G;
       const uint32_t s0 = a.start[row + x0], s1 = a.start[row + x1 + 1];
-      for (uint32_t j = s0 + lane; j < s1; j += 64) {
+      // two records per lane per pass: both loads are in flight together
+      for (uint32_t j = s0 + lane; j < s1; j += 128) {
+        const uint32_t j2 = j + 64;
+        const bool two = j2 < s1;
         const float4 p = a.ra[j];
-        const float dx = p.x - x.x, dy = p.y - x.y, dz = p.z - x.z;
+        const float4 p2 = two ? a.ra[j2] : p;
+        float dx = p.x - x.x, dy = p.y - x.y, dz = p.z - x.z;
         f(dx * dx + dy * dy + dz * dz, j);
+        if (two) {
+          dx = p2.x - x.x;
+          dy = p2.y - x.y;
+          dz = p2.z - x.z;
+          f(dx * dx + dy * dy + dz * dz, j2);
+        }
       }
     }
   }
