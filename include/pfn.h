@@ -310,7 +310,7 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  * to the order of FP32 additions):
  *   PFN_STRATEGY_FUSED: one kernel marches, evaluates the field on the matrix cores inside the
  *     march loop and composites (the only form the persistent and graph launches use);
- *   PFN_STRATEGY_WAVEFRONT: rounds of a march kernel that stores up to 16 field queries per ray,
+ *   PFN_STRATEGY_WAVEFRONT: rounds of a march kernel that stores up to 32 field queries per ray,
  *     level-major position-encoding kernels (each fine hashed level alone, so that its table
  *     stays in L2) and a matrix-core field kernel per 16-query ray tile; a batch runs one pass
  *     of rounds per field slot it reads; never captured in graphs (the graph setting of
@@ -320,9 +320,10 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  *   PFN_STRATEGY_WAVEFRONT_SERIAL: the same rounds, all on the context's stream;
  *   PFN_STRATEGY_AUTO (default): the wavefront form, unless graph replay was asked for (then
  *     the fused kernel).
- * Device buffers of the wavefront form (two sets of about 1.5 KB per ray of a round, at most 2^21
- * rays per round, plus 24 B per ray sample of the frame) are kept in the context and grown on
- * demand.  Both wavefront variants give bit-identical images. */
+ * Device buffers of the wavefront form (two sets of about 2.9 KB per ray of a round with 16-bit
+ * features, 5 KB with FP32, at most 2^21 rays per round, plus 24 B per ray sample of the frame)
+ * are kept in the context and grown on demand.  Both wavefront variants give bit-identical
+ * images. */
 typedef enum {
   PFN_STRATEGY_AUTO = 0,
   PFN_STRATEGY_FUSED = 1,

@@ -29,6 +29,9 @@
 // ray gets, so frames are deterministic.
 #include "wavefront.h"
 
+#define FI_GROUP 16  // samples of a pixel per ray of the layout (fixes the NEE random numbers)
+static_assert(FI_GROUP <= WF_SLOTS, "a sample group must fit the query slots of an entry");
+
 #ifndef FI_GROUPED_QUERIES
 #define FI_GROUPED_QUERIES (1 << 21)  // query slots from which the encoding runs per level group
 #endif
@@ -118,7 +121,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_sample_kernel(FiArgs a) {
       const f3 eye = {job.eye[0], job.eye[1], job.eye[2]};
       if (clip_cube(eye, d, t0, t1) && a.majorant > 0.0f) {
         const uint64_t pix = (uint64_t)py * (uint64_t)job.width + (uint64_t)px;
-        const int s0 = grp * WF_SLOTS, s1 = min(a.spp, s0 + WF_SLOTS);
+        const int s0 = grp * FI_GROUP, s1 = min(a.spp, s0 + FI_GROUP);
         for (int smp = s0; smp < s1; ++smp) {
           Philox rng;
           rng.init(job.seed, pix * (uint64_t)a.spp + (uint64_t)smp, STREAM_FI_SAMPLE);
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_nee_kernel(FiArgs a) {
     const f3 x = {a.qx[q], a.qy[q], a.qz[q]};
     const f3 alb = {a.wr[q], a.wg[q], a.wb[q]};
     Philox rng;
-    rng.init(job.seed, pix * (uint64_t)a.spp + (uint64_t)(grp * WF_SLOTS + k), STREAM_FI_NEE);
+    rng.init(job.seed, pix * (uint64_t)a.spp + (uint64_t)(grp * FI_GROUP + k), STREAM_FI_NEE);
     f3 Ld = {0.f, 0.f, 0.f};
     for (int l = 0; l < a.m.n_lights; ++l) {
       if (!((job.light_mask >> l) & 1)) continue;
@@ -242,7 +245,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
                                  int indirect, int prec, int slot, const FieldDev &fd_host) {
   WfState &w = ctx->wf;
   const int spp = job.spp;
-  const int groups = (spp + WF_SLOTS - 1) / WF_SLOTS;
+  const int groups = (spp + FI_GROUP - 1) / FI_GROUP;
   const int64_t rays = (int64_t)groups * job.tiles * 64;
   const int64_t pixels = (int64_t)job.width * job.height;
   if (rays >= (int64_t)1 << 31)
@@ -341,7 +344,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
       e.n_slots = wf_slots(a.n_entries);
       e.n_entries = a.n_entries;
       e.kshift = 0;  // entries hold min(spp, 16) collisions at most
-      while ((1 << e.kshift) < std::min(spp, WF_SLOTS)) ++e.kshift;
+      while ((1 << e.kshift) < std::min(spp, FI_GROUP)) ++e.kshift;
       WfDirArgs dg{};
       dg.F = m.fields + slot;
       dg.ent_cnt = b.ent_cnt;

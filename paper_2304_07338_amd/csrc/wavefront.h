@@ -11,7 +11,10 @@
 #include "pfn_ctx.h"
 
 #define WF_THREADS 256
-#define WF_SLOTS 16                  // queries per ray per round: one matrix-core tile
+#ifndef WF_SLOTS_LOG2
+#define WF_SLOTS_LOG2 5
+#endif
+#define WF_SLOTS (1 << WF_SLOTS_LOG2)  // queries per ray per round
 #define WF_MAX_ENTRIES (1 << 21)     // rays per round
 #define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
 #ifndef WF_GROUP_BYTES
@@ -22,10 +25,12 @@
 // write slot k of 64 consecutive entries, and 16 neighbouring rays' slot k are 64 contiguous
 // bytes for the field kernel.
 __host__ __device__ __forceinline__ int64_t wf_slot(int64_t t, int k) {
-  return ((t >> 6) << 10) | ((int64_t)k << 6) | (t & 63);
+  return ((t >> 6) << (6 + WF_SLOTS_LOG2)) | ((int64_t)k << 6) | (t & 63);
 }
 // Slots spanned by the first n entries.
-__host__ __device__ __forceinline__ int64_t wf_slots(int64_t n) { return ((n + 63) >> 6) << 10; }
+__host__ __device__ __forceinline__ int64_t wf_slots(int64_t n) {
+  return ((n + 63) >> 6) << (6 + WF_SLOTS_LOG2);
+}
 
 struct WfEncArgs {
   const FieldDev *F;
@@ -34,7 +39,7 @@ struct WfEncArgs {
   void *feat;           // [level][slot]: uint32 (two 16-bit features) or float2 (FP32)
   int64_t n_slots;
   int n_entries;
-  int kshift;           // entries hold at most 2^kshift queries (4: any count up to WF_SLOTS)
+  int kshift;           // entries hold at most 2^kshift queries (WF_SLOTS_LOG2: any count)
   int l0, l1;
   int per_level;        // 0: a thread encodes levels l0..l1-1 of its query; > 0: a thread
                         // encodes one level, per_level threads per level, level-major

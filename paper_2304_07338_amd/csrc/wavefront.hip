@@ -10,11 +10,13 @@
 //      WF_SLOTS queries the ray stops and is appended to the list of rays continued next round.
 //   2. wf_encode_kernel: the position encoding of every stored query, written level-major as
 //      the 16-bit (or FP32) features the matrix cores consume.  One launch covers the coarse
-//      levels; each fine hashed level (cells smaller than the spacing of neighbouring queries)
-//      gets a launch of its own so that its 2 MB table is the only grid table the L2 holds.
+//      levels; the fine hashed levels (cells smaller than the spacing of neighbouring queries)
+//      run two per launch, one on each half of the XCDs, so that each XCD's L2 holds one 2 MB
+//      table.
 //      wf_dir_kernel encodes the view direction once per ray of the round.
-//   3. wf_field_kernel: one wave per ray of the round: the MLP of its 16 queries on the matrix
-//      cores, the Eq. (7) decode, and the sum of W * L_i over the queries in a fixed order.
+//   3. wf_field_kernel: a wave takes 16 rays of the round: the MLP of their queries on the
+//      matrix cores, one 16-query tile per query index, the Eq. (7) decode, and each ray's sum of
+//      W * L_i over its queries in a fixed order.
 //   4. after the last round, wf_resolve_kernel averages each pixel's samples.
 //
 // A ray carries its direct sum and its indirect sum in the list from round to round and
@@ -287,8 +289,8 @@ __global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
 }
 
 // Field kernel: a wave takes 16 neighbouring rays of the round (entries t0..t0+15, one per
-// matrix-core column) and runs one tile per query index k = 0..15: column c of tile k is query k
-// of ray t0+c.  Lane group q holds levels 4q..4q+3 of its column's features; the direction
+// matrix-core column) and runs one tile per query index k < WF_SLOTS: column c of tile k is
+// query k of ray t0+c.  Lane group q holds levels 4q..4q+3 of its column's features; the direction
 // features of a column's ray are loaded once for all tiles.  Each column accumulates W * L_i of
 // its ray over k in order, in the lanes of group 0.
 template <int P>
@@ -768,7 +770,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     e.feat = b.feat;
     e.n_slots = wf_slots(n_in);
     e.n_entries = n_in;
-    e.kshift = 4;
+    e.kshift = WF_SLOTS_LOG2;
     WfDirArgs dg{};
     dg.F = m.fields + slot;
     dg.ent_cnt = b.ent_cnt;

@@ -4,7 +4,7 @@ matrix-core field tiles) against the fused kernel and the FP64 oracle.
 Both forms run the same per-ray arithmetic; they differ in the order in which the FP32 terms
 W * L_i are added to a pixel, so they agree to FP32 rounding (bar: relative RMSE 1e-5) and give
 identical march-step and query counts.  Cases cover many rounds per ray (stride 1, where a ray
-stores up to 16 queries per round), frames of more ray samples than one round holds (2^21),
+stores up to 32 queries per round), frames of more ray samples than one round holds (2^21),
 ragged tiles, several samples per pixel, every matrix-core precision, both direct-light modes,
 and a batch of jobs that must render exactly as its jobs do alone."""
 import numpy as np
