@@ -16,7 +16,7 @@
 #endif
 #define WF_SLOTS (1 << WF_SLOTS_LOG2)  // queries per ray per round
 #define WF_MAX_ENTRIES (1 << 21)     // rays per round
-#define WF_FINE_RES 512              // hashed levels at or above this resolution run alone
+#define WF_FINE_RES 1024             // hashed levels from this resolution on are encoded apart
 #ifndef WF_GROUP_BYTES
 #define WF_GROUP_BYTES (64u << 20)   // table bytes the coarse levels of one encoding launch span
 #endif
@@ -96,7 +96,8 @@ __device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, in
 // `feat_bytes` bytes; kept between frames and grown on demand.
 hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes);
 // Level groups of the position encoding of field slot `slot`: the coarse levels together (up to
-// WF_GROUP_BYTES of tables), each fine hashed level alone.
+// WF_GROUP_BYTES of tables), each fine hashed level alone (the ray marcher then encodes
+// consecutive fine levels in one launch, each on its own XCDs).
 std::vector<std::pair<int, int>> wf_level_groups(const pfn_context *ctx, int slot,
                                                  const FieldDev &fd_host, size_t feat_bytes);
 // Field-kernel workgroups that are resident on the device at once.

@@ -11,8 +11,8 @@
 //   2. wf_encode_kernel: the position encoding of every stored query, written level-major as
 //      the 16-bit (or FP32) features the matrix cores consume.  One launch covers the coarse
 //      levels; the fine hashed levels (cells smaller than the spacing of neighbouring queries)
-//      run two per launch, one on each half of the XCDs, so that each XCD's L2 holds one 2 MB
-//      table.
+//      run up to four per launch, each on its own two XCDs, so that each XCD's L2 holds one
+//      2 MB table.
 //      wf_dir_kernel encodes the view direction once per ray of the round.
 //   3. wf_field_kernel: a wave takes 16 rays of the round: the MLP of their queries on the
 //      matrix cores, one 16-query tile per query index, the Eq. (7) decode, and each ray's sum of
@@ -27,7 +27,7 @@
 #include "wavefront.h"
 
 #ifndef WF_XCD_LEVELS
-#define WF_XCD_LEVELS 2  // fine levels per encoding launch, each on 8 / WF_XCD_LEVELS XCDs
+#define WF_XCD_LEVELS 4  // fine levels per encoding launch, each on 8 / WF_XCD_LEVELS XCDs
 #endif
 
 struct WfList {
