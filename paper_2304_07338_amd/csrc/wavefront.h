@@ -45,6 +45,8 @@ struct WfEncArgs {
                         // encodes one level, per_level threads per level, level-major
   int xcd_levels;       // 2 or 4: levels l0 .. l0 + xcd_levels - 1, each on its own 8 /
                         // xcd_levels XCDs, so that each XCD's L2 holds one level's table
+  int paired;           // 1: all levels 0 .. l1-1 (8 <= l1 <= 16) in one launch; XCD x encodes
+                        // level x and, if it is 8 or more, level l1 - 1 - x
 };
 
 struct WfDirArgs {

@@ -9,10 +9,10 @@
 //      the query (position of the group's first step, W) in the ray's next slot.  After
 //      WF_SLOTS queries the ray stops and is appended to the list of rays continued next round.
 //   2. wf_encode_kernel: the position encoding of every stored query, written level-major as
-//      the 16-bit (or FP32) features the matrix cores consume.  One launch covers the coarse
-//      levels; the fine hashed levels (cells smaller than the spacing of neighbouring queries)
-//      run up to four per launch, each on its own two XCDs, so that each XCD's L2 holds one
-//      2 MB table.
+//      the 16-bit (or FP32) features the matrix cores consume.  One launch covers all levels:
+//      XCD x encodes level x and level L-1-x, a coarse level whose neighbouring queries share
+//      cells with a fine one whose queries each touch their own cache lines, so that the XCDs
+//      carry similar loads and each XCD's L2 holds at most two 2 MB tables.
 //      wf_dir_kernel encodes the view direction once per ray of the round.
 //   3. wf_field_kernel: a wave takes 16 rays of the round: the MLP of their queries on the
 //      matrix cores, one 16-query tile per query index, the Eq. (7) decode, and each ray's sum of
@@ -27,7 +27,8 @@
 #include "wavefront.h"
 
 #ifndef WF_XCD_LEVELS
-#define WF_XCD_LEVELS 4  // fine levels per encoding launch, each on 8 / WF_XCD_LEVELS XCDs
+#define WF_XCD_LEVELS 4  // without pairing: fine levels per encoding launch, each on
+                         // 8 / WF_XCD_LEVELS XCDs
 #endif
 
 struct WfList {
@@ -252,7 +253,14 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   // with per_level, one level of it)
   int64_t g = (int64_t)blockIdx.x * WF_THREADS + threadIdx.x;
   int l0 = e.l0, l1 = e.l1;
-  if (e.xcd_levels) {
+  if (e.paired) {
+    // workgroups go to the XCDs round-robin: blockIdx % 8 is the XCD, which encodes level
+    // l0 = x and, when it is not another XCD's own level, level l1 = L - 1 - x
+    const int xcd = (int)(blockIdx.x & 7);
+    g = (int64_t)(blockIdx.x >> 3) * WF_THREADS + threadIdx.x;
+    l0 = xcd;
+    l1 = e.l1 - 1 - xcd;
+  } else if (e.xcd_levels) {
     // workgroups go to the XCDs round-robin: blockIdx % 8 is the XCD; level l0 + j runs on the
     // per = 8 / xcd_levels XCDs j * per .. j * per + per - 1
     const int xcd = (int)(blockIdx.x & 7), per = 8 / e.xcd_levels;
@@ -272,6 +280,15 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   const int64_t s = wf_slot(t, c);
   const FieldDev &F = *e.F;
   const f3 x = clamp01(f3{e.qx[s], e.qy[s], e.qz[s]});
+  if (e.paired) {
+    // both levels' corner reads are issued before either store
+    const bool two = l1 >= 8;
+    const float2 va = encode_pos_level<P>(F, l0, x);
+    const float2 vb = encode_pos_level<P>(F, two ? l1 : l0, x);
+    store_feat<P>(e.feat, (int64_t)l0 * e.n_slots + s, va);
+    if (two) store_feat<P>(e.feat, (int64_t)l1 * e.n_slots + s, vb);
+    return;
+  }
   for (int lv = l0; lv < l1; ++lv)
     store_feat<P>(e.feat, (int64_t)lv * e.n_slots + s, encode_pos_level<P>(F, lv, x));
 }
@@ -563,12 +580,19 @@ static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, con
     ee.l0 = g.first;
     ee.l1 = g.second;
     // fine levels spread over the XCDs are marked by a negative end: -(level count)
-    ee.xcd_levels = g.second < 0 ? -g.second : 0;
+    // all levels paired over the XCDs in one launch are marked by a negative start
+    ee.paired = g.first < 0 ? 1 : 0;
+    if (ee.paired) ee.l0 = 0;
+    ee.xcd_levels = !ee.paired && g.second < 0 ? -g.second : 0;
     if (ee.xcd_levels) ee.l1 = g.first + ee.xcd_levels;
-    ee.per_level = !ee.xcd_levels && split_levels && g.second - g.first > 1 ? (int)threads : 0;
+    ee.per_level = !ee.paired && !ee.xcd_levels && split_levels && g.second - g.first > 1
+                       ? (int)threads
+                       : 0;
     const int64_t n = ee.per_level ? threads * (g.second - g.first) : threads;
     int eb = (int)((n + WF_THREADS - 1) / WF_THREADS);
-    if (ee.xcd_levels) {
+    if (ee.paired) {
+      eb *= 8;
+    } else if (ee.xcd_levels) {
       const int per = 8 / ee.xcd_levels;
       eb = 8 * ((eb + per - 1) / per);
     }
@@ -684,7 +708,10 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
 
   std::vector<std::pair<int, int>> groups;
-  {
+  if (fd_host.levels >= 8 && fd_host.levels <= 16) {
+    // one launch, the levels paired over the XCDs; marked by a negative start
+    groups.push_back({-1, fd_host.levels});
+  } else {
     // runs of single fine levels go WF_XCD_LEVELS (then 2) at a time, each level on its own
     // share of the XCDs; marked by the end -(level count)
     const std::vector<std::pair<int, int>> g0 = wf_level_groups(ctx, slot, fd_host, fbytes);

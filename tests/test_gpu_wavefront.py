@@ -100,6 +100,31 @@ def test_wavefront_matches_oracle(orc, wctx):
     assert err <= 2e-3  # the light-transmittance volume is stored in binary16
 
 
+@pytest.mark.parametrize("levels", [12, 8, 6])
+def test_wavefront_level_counts(wctx, levels):
+    """8 to 16 levels are encoded in one launch with the levels paired over the XCDs (with 12
+    levels, four XCDs hold two levels and four hold one); fewer levels take the grouped
+    launches.  Either way the image and counts equal the fused kernel's."""
+    import torch
+    from paper_2304_07338_amd.pfn import FieldConfig
+    ctx = wctx["ctx"]
+    ctx.field_select(2)
+    ctx.field_init(FieldConfig(levels=levels, log2_table=14), seed=6)
+    p = ctx.field_get_params()
+    g = torch.Generator(device="cuda:0").manual_seed(6)
+    ctx.field_set_params((p + 0.3 * torch.rand(p.shape, device="cuda:0", generator=g) - 0.15)
+                         .contiguous())
+    ctx.field_set_kappa(1e-2)
+    cam = sg.make_camera(wctx["w"].seed, 25, 48, 36)
+    r = _both(ctx, cam, _cfg(spp=2, field_slot=2))
+    (a, ca), (b, cb) = r["fused"], r["wavefront"]
+    err = rel_rmse(b, a)
+    say(f"  {levels} levels: wavefront vs fused rel-RMSE {err:.2e}, mean {a.mean():.4g}")
+    assert a.mean() > 0
+    assert tuple(ca) == tuple(cb)
+    assert err <= 1e-5
+
+
 def test_wavefront_frame_larger_than_one_round(wctx):
     """1280 x 960 at 2 spp is 2,457,600 ray samples: more than the 2^21 rays of a round, so fresh
     rays enter over two rounds while the first rays continue."""
