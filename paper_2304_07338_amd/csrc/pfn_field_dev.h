@@ -256,25 +256,36 @@ __device__ __forceinline__ f32x4 relu4(f32x4 v) {
   return f32x4{fmaxf(v[0], 0.0f), fmaxf(v[1], 0.0f), fmaxf(v[2], 0.0f), fmaxf(v[3], 0.0f)};
 }
 
-// Forward pass of one 16-query tile at 16-bit precision.  w: packed weights in LDS (vec units);
-// b0 = position features, b1 = direction features, b2 = (g, 0, ...) for lane group 0.
-// Returns the output tile: lanes 0..15 hold (L'_r, L'_g, L'_b, 0) of query l.
+// Forward pass of one 16-query tile at 16-bit precision, in two parts.  w: packed weights in
+// LDS (vec units); b0 = position features, b1 = direction features, b2 = (g, 0, ...) for lane
+// group 0.  The input layer adds the direction and g products first and the position product
+// last, so that a caller whose tiles share b1 and b2 (one ray per column) computes the first
+// part once and gets the same bits.
 template <int P>
-__device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__restrict__ w,
-                                               int hidden, typename Mma<P>::vec b0,
-                                               typename Mma<P>::vec b1, typename Mma<P>::vec b2) {
+__device__ __forceinline__ void mlp_input16(const typename Mma<P>::vec *__restrict__ w,
+                                            typename Mma<P>::vec b1, typename Mma<P>::vec b2,
+                                            f32x4 pre[4]) {
+  typedef Mma<P> M;
+  const int l = lane_id();
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+    a = M::mma(w[(mt * 3 + 1) * 64 + l], b1, a);
+    pre[mt] = M::mma(w[(mt * 3 + 2) * 64 + l], b2, a);
+  }
+}
+
+// Second part: the position product, the hidden layers and the output layer.  Returns the
+// output tile: lanes 0..15 hold (L'_r, L'_g, L'_b, 0) of query l.
+template <int P>
+__device__ __forceinline__ f32x4 mlp_rest16(const typename Mma<P>::vec *__restrict__ w, int hidden,
+                                            typename Mma<P>::vec b0, const f32x4 pre[4]) {
   typedef Mma<P> M;
   typedef typename M::vec vec;
   const int l = lane_id();
   f32x4 acc[4];
 #pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
-    a = M::mma(w[(mt * 3 + 0) * 64 + l], b0, a);
-    a = M::mma(w[(mt * 3 + 1) * 64 + l], b1, a);
-    a = M::mma(w[(mt * 3 + 2) * 64 + l], b2, a);
-    acc[mt] = relu4(a);
-  }
+  for (int mt = 0; mt < 4; ++mt) acc[mt] = relu4(M::mma(w[(mt * 3 + 0) * 64 + l], b0, pre[mt]));
   const vec *wl = w + 12 * 64;
   for (int h = 1; h < hidden; ++h) {
     float t0[8], t1[8];
@@ -308,6 +319,15 @@ __device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__res
   out = M::mma(wl[0 * 64 + l], h0, out);
   out = M::mma(wl[1 * 64 + l], h1, out);
   return out;
+}
+
+template <int P>
+__device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__restrict__ w,
+                                               int hidden, typename Mma<P>::vec b0,
+                                               typename Mma<P>::vec b1, typename Mma<P>::vec b2) {
+  f32x4 pre[4];
+  mlp_input16<P>(w, b1, b2, pre);
+  return mlp_rest16<P>(w, hidden, b0, pre);
 }
 
 // FP32 variant on v_mfma_f32_16x16x4f32: one K=4 chunk per instruction; chunk c of the input

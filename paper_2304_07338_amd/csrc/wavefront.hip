@@ -16,7 +16,8 @@
 //      wf_dir_kernel encodes the view direction once per ray of the round.
 //   3. wf_field_kernel: a wave takes 16 rays of the round: the MLP of their queries on the
 //      matrix cores, one 16-query tile per query index, the Eq. (7) decode, and each ray's sum of
-//      W * L_i over its queries in a fixed order.
+//      W * L_i over its queries in a fixed order.  The input layer's direction and g products
+//      are the same for all tiles of the 16 rays and are computed once.
 //   4. after the last round, wf_resolve_kernel averages each pixel's samples.
 //
 // A ray carries its direct sum and its indirect sum in the list from round to round and
@@ -310,8 +311,11 @@ __global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
 // query k of ray t0+c.  Lane group q holds levels 4q..4q+3 of its column's features; the direction
 // features of a column's ray are loaded once for all tiles.  Each column accumulates W * L_i of
 // its ray over k in order, in the lanes of group 0.
+// The 16-bit weights take 30 KB of LDS per workgroup, so 5 waves per SIMD are resident; the
+// register budget is held to that occupancy.
 template <int P>
-__global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
+__global__ __launch_bounds__(WF_THREADS) __attribute__((amdgpu_waves_per_eu(5, 8)))
+void wf_field_kernel(WfFieldArgs a) {
   extern __shared__ __align__(16) unsigned char lds_w[];
   stage_weights(lds_w, a.mlp, a.mlp_bytes);
   __syncthreads();
@@ -396,6 +400,10 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
       const vec b1 = __builtin_bit_cast(vec, dw);
       float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
       const vec b2 = M::pack(gz);
+      // the direction and g products of the input layer are the same for every query of a
+      // column's ray: computed once per tile of rays
+      f32x4 pre[4];
+      mlp_input16<P>(reinterpret_cast<const vec *>(lds_w), b1, b2, pre);
       // the loads of query k+1 are issued before the network of query k runs
       auto load_k = [&](int k, u32x4 &pw, f3 &W) {
         pw = u32x4{0u, 0u, 0u, 0u};
@@ -417,8 +425,8 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field_kernel(WfFieldArgs a) {
         const u32x4 pc = pw;
         const f3 Wc = W;
         if (k + 1 < kmax) load_k(k + 1, pw, W);
-        const f32x4 out = mlp_forward16<P>(reinterpret_cast<const vec *>(lds_w) + wofs, F.hidden,
-                                           __builtin_bit_cast(vec, pc), b1, b2);
+        const f32x4 out = mlp_rest16<P>(reinterpret_cast<const vec *>(lds_w) + wofs, F.hidden,
+                                        __builtin_bit_cast(vec, pc), pre);
         if (q == 0 && k < cnt) {
           S.x = fmaf(Wc.x, decode_lp(out[0], F.psi, F.kappa), S.x);
           S.y = fmaf(Wc.y, decode_lp(out[1], F.psi, F.kappa), S.y);
