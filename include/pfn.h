@@ -311,12 +311,13 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  *   PFN_STRATEGY_FUSED: one kernel marches, evaluates the field on the matrix cores inside the
  *     march loop and composites (the only form the persistent and graph launches use);
  *   PFN_STRATEGY_WAVEFRONT: rounds of a march kernel that stores up to 32 field queries per ray,
- *     level-major position-encoding kernels (each fine hashed level alone, so that its table
- *     stays in L2) and a matrix-core field kernel per 16-query ray tile; a batch runs one pass
+ *     level-major position-encoding kernels (each XCD encoding two levels, so that their
+ *     tables stay in its L2) and a matrix-core field kernel per 16-query ray tile; a batch runs one pass
  *     of rounds per field slot it reads; never captured in graphs (the graph setting of
  *     pfn_set_launch_mode applies to the fused kernel only);
  *     the march kernel of the next round runs on the context's stream while this round's
- *     encoding and field kernels run on a second stream the library owns (default priority);
+ *     encoding kernels run on a second stream and its field kernel on a third (both owned by
+ *     the library, default priority), beside the next round's encodings;
  *   PFN_STRATEGY_WAVEFRONT_SERIAL: the same rounds, all on the context's stream;
  *   PFN_STRATEGY_AUTO (default): the wavefront form, unless graph replay was asked for (then
  *     the fused kernel).

@@ -378,7 +378,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
       // groups keep each fine table resident in L2
       const bool grouped = ((int64_t)a.n_entries << e.kshift) >= FI_GROUPED_QUERIES;
       const std::vector<std::pair<int, int>> one = {{0, fd_host.levels}};
-      wf_launch_field_pass(ctx, sa, prec, e, dg, grouped ? lgroups : one, f, fb, true);
+      PFN_HIP(ctx, wf_launch_field_pass(ctx, sa, prec, e, dg, grouped ? lgroups : one, f, fb, true));
       PFN_HIP(ctx, hipGetLastError());
     }
     // the next chunk rewrites the entries: wait for the direct-light kernel

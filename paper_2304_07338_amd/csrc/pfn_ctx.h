@@ -103,8 +103,10 @@ struct WfState {
   unsigned *host_count = nullptr;              // pinned copies of the round counters
   int64_t *pix_begin = nullptr;
   size_t pix_cap = 0, ent_cap = 0, feat_elem = 0, acc_cap = 0;
-  hipStream_t side = nullptr;                  // encoding and field kernels
+  hipStream_t side = nullptr;                  // encoding kernels
+  hipStream_t side2 = nullptr;                 // field kernels
   hipEvent_t ev_march[2] = {nullptr, nullptr}, ev_field[2] = {nullptr, nullptr}, ev_done = nullptr;
+  hipEvent_t ev_enc[2] = {nullptr, nullptr};
 };
 
 #define PFN_TIMED_KERNELS 16

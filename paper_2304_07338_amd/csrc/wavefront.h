@@ -107,8 +107,12 @@ int wf_field_blocks(int prec, int mlp_bytes);
 // The encoding launches (one per level group), the direction encoding and the field kernel of
 // one round, on stream st.
 // split_levels: each group launch runs one thread per (level, query) instead of one per query.
-void wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
-                          const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
-                          const WfFieldArgs &f, int field_blocks, bool split_levels = false);
+// field_st: when set, the field kernel runs on that stream instead, after enc_done (recorded on
+// st once the encodings are done).
+hipError_t wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
+                                const WfDirArgs &dg,
+                                const std::vector<std::pair<int, int>> &groups,
+                                const WfFieldArgs &f, int field_blocks, bool split_levels = false,
+                                hipStream_t field_st = nullptr, hipEvent_t enc_done = nullptr);
 // Pixel averages over the ray samples of every job.
 void wf_launch_resolve(pfn_context *ctx, hipStream_t st, const WfResolveArgs &ra, int64_t pixels);

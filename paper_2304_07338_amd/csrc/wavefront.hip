@@ -547,9 +547,11 @@ hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes
   if (!w.side) {
     // default priority, and not synchronising with the null stream
     if ((e = hipStreamCreateWithFlags(&w.side, hipStreamNonBlocking))) return e;
+    if ((e = hipStreamCreateWithFlags(&w.side2, hipStreamNonBlocking))) return e;
     for (int i = 0; i < 2; ++i) {
       if ((e = hipEventCreateWithFlags(&w.ev_march[i], hipEventDisableTiming))) return e;
       if ((e = hipEventCreateWithFlags(&w.ev_field[i], hipEventDisableTiming))) return e;
+      if ((e = hipEventCreateWithFlags(&w.ev_enc[i], hipEventDisableTiming))) return e;
     }
     if ((e = hipEventCreateWithFlags(&w.ev_done, hipEventDisableTiming))) return e;
   }
@@ -558,6 +560,7 @@ hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes
 
 void wf_release(WfState &w) {
   if (w.side) (void)hipStreamSynchronize(w.side);
+  if (w.side2) (void)hipStreamSynchronize(w.side2);
   free_entries(w);
   free_p(w.acc_d);
   free_p(w.acc_i);
@@ -567,9 +570,11 @@ void wf_release(WfState &w) {
   for (int i = 0; i < 2; ++i) {
     if (w.ev_march[i]) (void)hipEventDestroy(w.ev_march[i]);
     if (w.ev_field[i]) (void)hipEventDestroy(w.ev_field[i]);
+    if (w.ev_enc[i]) (void)hipEventDestroy(w.ev_enc[i]);
   }
   if (w.ev_done) (void)hipEventDestroy(w.ev_done);
   if (w.side) (void)hipStreamDestroy(w.side);
+  if (w.side2) (void)hipStreamDestroy(w.side2);
   w = WfState{};
 }
 
@@ -579,9 +584,10 @@ static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
 }
 
 template <int P>
-static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, const WfDirArgs &dg,
-                       const std::vector<std::pair<int, int>> &groups, const WfFieldArgs &f,
-                       int field_blocks, bool split_levels) {
+static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e,
+                             const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
+                             const WfFieldArgs &f, int field_blocks, bool split_levels,
+                             hipStream_t fst, hipEvent_t enc_done) {
   const int64_t threads = (((int64_t)e.n_entries + 63) >> 6) << (6 + e.kshift);
   for (auto &g : groups) {
     WfEncArgs ee = e;
@@ -614,18 +620,31 @@ static void launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e, con
                        dim3(WF_THREADS), 0, st, dg);
     timing_end_on(ctx, ts, TK_WF_ENCODE, st);
   }
+  if (fst) {
+    hipError_t err = hipEventRecord(enc_done, st);
+    if (err == hipSuccess) err = hipStreamWaitEvent(fst, enc_done, 0);
+    if (err != hipSuccess) return err;
+    st = fst;
+  }
   const int ts = timing_begin_on(ctx, st);
   hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
                      (size_t)f.mlp_bytes, st, f);
   timing_end_on(ctx, ts, TK_WF_FIELD, st);
+  return hipSuccess;
 }
 
-void wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
-                          const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
-                          const WfFieldArgs &f, int field_blocks, bool split_levels) {
-  if (prec == P_F32) launch_k23<P_F32>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
-  else if (prec == P_BF16) launch_k23<P_BF16>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
-  else launch_k23<P_F16>(ctx, st, e, dg, groups, f, field_blocks, split_levels);
+hipError_t wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
+                                const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
+                                const WfFieldArgs &f, int field_blocks, bool split_levels,
+                                hipStream_t field_st, hipEvent_t enc_done) {
+  if (prec == P_F32)
+    return launch_k23<P_F32>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                             enc_done);
+  if (prec == P_BF16)
+    return launch_k23<P_BF16>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                              enc_done);
+  return launch_k23<P_F16>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                           enc_done);
 }
 
 template <int P>
@@ -681,10 +700,13 @@ void wf_launch_resolve(pfn_context *ctx, hipStream_t st, const WfResolveArgs &ra
 }
 
 // Rounds of the wavefront render.  The march kernel of round r runs on the context's stream;
-// the encoding and field kernels of round r run on a side stream once the march kernel has
-// finished, while the march kernel of round r+1 (which only needs the list of continuing rays)
-// already runs on the context's stream.  Round r+2 reuses round r's buffers, so its march
-// kernel waits for round r's field kernel.  With `overlap` off the side stream is not used.
+// the encoding kernels of round r run on a side stream once the march kernel has finished, and
+// its field kernel on a second side stream once they have, while the march kernel of round r+1
+// (which only needs the list of continuing rays) already runs on the context's stream and the
+// encodings of round r+1 may run beside the field kernel of round r.  Round r+2 reuses round
+// r's buffers, so its march kernel waits for round r's field kernel.  The field kernels follow
+// one another on their stream (each reads the indirect sums the previous one carried).  With
+// `overlap` off the side streams are not used.
 pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
                          int direct, int prec, int slot, const FieldDev &fd_host, bool overlap) {
   WfState &w = ctx->wf;
@@ -744,7 +766,9 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     }
   }
   const int fb_max = wf_field_blocks(prec, m.mlp_bytes);
-  hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream;
+  // march kernels on sa, encodings on sb, field kernels on sc
+  hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream,
+              sc = overlap ? w.side2 : ctx->stream;
 
   const int tslot = timing_begin(ctx);
   int64_t fresh_next = 0;
@@ -834,9 +858,10 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     f.out_ci = w.list_ci[cur ^ 1];
     const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));
     if (overlap) PFN_HIP(ctx, hipStreamWaitEvent(sb, w.ev_march[p], 0));
-    wf_launch_field_pass(ctx, sb, prec, e, dg, groups, f, fb);
+    PFN_HIP(ctx, wf_launch_field_pass(ctx, sb, prec, e, dg, groups, f, fb, false,
+                                      overlap ? w.side2 : nullptr, w.ev_enc[p]));
     PFN_HIP(ctx, hipGetLastError());
-    PFN_HIP(ctx, hipEventRecord(w.ev_field[p], sb));
+    PFN_HIP(ctx, hipEventRecord(w.ev_field[p], sc));
 
     // the next round needs the number of continuing rays
     PFN_HIP(ctx, hipEventSynchronize(w.ev_march[p]));
@@ -846,7 +871,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   }
   // the resolve reads every ray's final sums: after the last field kernel
   if (overlap) {
-    PFN_HIP(ctx, hipEventRecord(w.ev_done, sb));
+    PFN_HIP(ctx, hipEventRecord(w.ev_done, sc));
     PFN_HIP(ctx, hipStreamWaitEvent(sa, w.ev_done, 0));
   }
   WfResolveArgs ra{};
