@@ -137,6 +137,7 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx->vol);
+  dev_free(ctx->qvol);
   dev_free(ctx->tf_dev);
   dev_free(ctx->lightvol);
   dev_free(ctx->cache);
@@ -199,9 +200,11 @@ extern "C" pfn_status pfn_set_volume(pfn_context *ctx, const void *dev_density, 
   ARG(dtype == PFN_F32 || dtype == PFN_F16, "volume dtype must be F32 or F16");
   ARG(nx >= 2 && ny >= 2 && nz >= 2 && nx <= 4096 && ny <= 4096 && nz <= 4096,
       "volume sizes must be in [2, 4096]");
-  size_t elems = 0;
+  size_t elems = 0, qe = 0;
   BrickGrid g = make_brick_grid(nx, ny, nz, &elems);
-  ARG(elems < ((size_t)1 << 31), "volume too large for 32-bit brick offsets");
+  const BrickGrid qg = make_brick_grid(nx + 1, ny + 1, nz, &qe);
+  ARG(elems < ((size_t)1 << 31) && (dtype != PFN_F16 || qe < ((size_t)1 << 31)),
+      "volume too large for 32-bit brick offsets");
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   size_t es = dtype == PFN_F16 ? 2 : 4;
   if (!ctx->vol || ctx->vol_elems * (ctx->vol_dtype == PFN_F16 ? 2 : 4) < elems * es) {
@@ -214,6 +217,22 @@ extern "C" pfn_status pfn_set_volume(pfn_context *ctx, const void *dev_density, 
   ctx->vol_dtype = dtype;
   ctx->nmax = std::max(nx, std::max(ny, nz));
   PFN_HIP(ctx, launch_brick_volume(ctx, dev_density, dtype, nx, ny, nz));
+  if (dtype == PFN_F16) {
+    // the march kernels' two-load density lookups (8 bytes per cell, 4x the volume)
+    if (!ctx->qvol || ctx->qvol_elems < qe) {
+      dev_free(ctx->qvol);
+      ctx->qvol = nullptr;
+      ctx->qvol_elems = 0;
+      PFN_HIP(ctx, dev_alloc((void **)&ctx->qvol, qe * sizeof(uint2)));
+      ctx->qvol_elems = qe;
+    }
+    ctx->qvol_grid = qg;
+    PFN_HIP(ctx, launch_quad_volume(ctx));
+  } else {
+    dev_free(ctx->qvol);
+    ctx->qvol = nullptr;
+    ctx->qvol_elems = 0;
+  }
   ctx->lv_valid = false;
   return PFN_OK;
 }
@@ -667,6 +686,8 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
   MarchArgs a{};
   a.vol = ctx->vol;
   a.vg = ctx->vol_grid;
+  a.qvol = ctx->vol_dtype == PFN_F16 ? ctx->qvol : nullptr;
+  a.qg = ctx->qvol_grid;
   a.tf = ctx->tf_dev;
   a.ext_scale = ctx->ext_scale;
   a.n_lights = ctx->n_lights;

@@ -29,6 +29,8 @@ struct MarchJob {
 struct MarchArgs {
   const void *vol;
   BrickGrid vg;
+  const uint2 *qvol;  // binary16 volumes: quad copy for two-load lookups (else null)
+  BrickGrid qg;
   const float4 *tf;
   float ext_scale;
   int n_lights;

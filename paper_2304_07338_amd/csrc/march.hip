@@ -163,7 +163,7 @@ __device__ __forceinline__ void march_block(const MarchArgs &a, const MarchJob &
         }
         float t = t0 + (float)j * job.step + xi * l;
         f3 x = eye + d * t;
-        float rho = density_at(reinterpret_cast<const VT *>(a.vol), a.vg, x);
+        float rho = density_march(reinterpret_cast<const VT *>(a.vol), a.vg, a.qvol, a.qg, x);
         float4 o = tf_lookup(tf, rho);
         float sig = o.w * a.ext_scale;
         float alpha = -expm1f(-sig * l);

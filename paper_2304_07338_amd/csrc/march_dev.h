@@ -29,7 +29,7 @@ __device__ __forceinline__ float4 tri_fetch4(const ushort4 *__restrict__ p, cons
 
 template <typename VT>
 __device__ __forceinline__ float sigma_at(const MarchArgs &a, const float4 *tf, f3 x) {
-  float rho = density_at(reinterpret_cast<const VT *>(a.vol), a.vg, x);
+  float rho = density_march(reinterpret_cast<const VT *>(a.vol), a.vg, a.qvol, a.qg, x);
   return tf_lookup(tf, rho).w * a.ext_scale;
 }
 

@@ -121,6 +121,9 @@ struct pfn_context {
   pfn_dtype vol_dtype = PFN_F32;
   BrickGrid vol_grid{};
   size_t vol_elems = 0;
+  uint2 *qvol = nullptr;     // binary16 volumes: the four (x, y) corners of every cell
+  BrickGrid qvol_grid{};     // (sizes nx+1, ny+1, nz), for two-load density lookups
+  size_t qvol_elems = 0;
   int nmax = 0;
   float4 *tf_dev = nullptr;
   float tf_host[1024] = {};
@@ -219,6 +222,7 @@ int timing_begin_on(pfn_context *ctx, hipStream_t stream);
 void timing_end_on(pfn_context *ctx, int slot, int kernel, hipStream_t stream);
 
 // Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
+hipError_t launch_quad_volume(pfn_context *ctx);
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
                                int nz);
 hipError_t launch_light_volume(pfn_context *ctx, float step);

@@ -249,17 +249,25 @@ __device__ __forceinline__ float to_f<__half>(__half v) {
   return __half2float(v);
 }
 
+// Trilinear blend of the 8 corner values (x fastest), with the roundings spelled out so that
+// every lookup form gives the same bits.
+__device__ __forceinline__ float trilerp8(float c000, float c100, float c010, float c110,
+                                          float c001, float c101, float c011, float c111,
+                                          float fx, float fy, float fz) {
+  const float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float c00 = fmaf(fx, c100, gx * c000), c10 = fmaf(fx, c110, gx * c010);
+  const float c01 = fmaf(fx, c101, gx * c001), c11 = fmaf(fx, c111, gx * c011);
+  const float c0 = fmaf(fy, c10, gy * c00), c1 = fmaf(fy, c11, gy * c01);
+  return fmaf(fz, c1, gz * c0);
+}
+
 template <typename T>
 __device__ __forceinline__ float tri_fetch(const T *__restrict__ p, const Tri &t) {
-  float c000 = to_f(p[t.ox0 + t.oy0 + t.oz0]), c100 = to_f(p[t.ox1 + t.oy0 + t.oz0]);
-  float c010 = to_f(p[t.ox0 + t.oy1 + t.oz0]), c110 = to_f(p[t.ox1 + t.oy1 + t.oz0]);
-  float c001 = to_f(p[t.ox0 + t.oy0 + t.oz1]), c101 = to_f(p[t.ox1 + t.oy0 + t.oz1]);
-  float c011 = to_f(p[t.ox0 + t.oy1 + t.oz1]), c111 = to_f(p[t.ox1 + t.oy1 + t.oz1]);
-  float gx = 1.0f - t.fx, gy = 1.0f - t.fy, gz = 1.0f - t.fz;
-  float c00 = gx * c000 + t.fx * c100, c10 = gx * c010 + t.fx * c110;
-  float c01 = gx * c001 + t.fx * c101, c11 = gx * c011 + t.fx * c111;
-  float c0 = gy * c00 + t.fy * c10, c1 = gy * c01 + t.fy * c11;
-  return gz * c0 + t.fz * c1;
+  return trilerp8(to_f(p[t.ox0 + t.oy0 + t.oz0]), to_f(p[t.ox1 + t.oy0 + t.oz0]),
+                  to_f(p[t.ox0 + t.oy1 + t.oz0]), to_f(p[t.ox1 + t.oy1 + t.oz0]),
+                  to_f(p[t.ox0 + t.oy0 + t.oz1]), to_f(p[t.ox1 + t.oy0 + t.oz1]),
+                  to_f(p[t.ox0 + t.oy1 + t.oz1]), to_f(p[t.ox1 + t.oy1 + t.oz1]), t.fx, t.fy,
+                  t.fz);
 }
 
 __device__ __forceinline__ bool inside_cube(f3 x) {
@@ -270,6 +278,43 @@ template <typename T>
 __device__ __forceinline__ float density_at(const T *__restrict__ vol, const BrickGrid &g, f3 x) {
   if (!inside_cube(x)) return 0.0f;
   return tri_fetch(vol, tri_setup(g, x));
+}
+
+// Index of the quad copy of a binary16 volume along x or y: the cell's lower corner plus one
+// (0 .. n), recovered from the clamped corners of tri_axis (lower corner -1 gives 0 0, n-1
+// gives n-1 n-1).
+__device__ __forceinline__ int quad_axis(int i0, int i1, int n) {
+  return (i0 == i1 && i1 == n - 1) ? n : i1;
+}
+
+// density_at for a binary16 volume from its quad copy q (grid qg, sizes nx+1, ny+1, nz): entry
+// (a, b, k) holds the values at x corners a-1, a and y corners b-1, b (clamped) of plane k, so
+// one 8-byte load per z plane gives four corners.  Same corners, weights and blend as
+// density_at.
+__device__ __forceinline__ float density_at_quad(const uint2 *__restrict__ q, const BrickGrid &qg,
+                                                 const BrickGrid &g, f3 x) {
+  if (!inside_cube(x)) return 0.0f;
+  int i0, i1, j0, j1, k0, k1;
+  float fx, fy, fz;
+  tri_axis(x.x, g.nx, i0, i1, fx);
+  tri_axis(x.y, g.ny, j0, j1, fy);
+  tri_axis(x.z, g.nz, k0, k1, fz);
+  const int oxy = brick_ox(quad_axis(i0, i1, g.nx)) + brick_oy(qg, quad_axis(j0, j1, g.ny));
+  const uint2 p0 = q[oxy + brick_oz(qg, k0)], p1 = q[oxy + brick_oz(qg, k1)];
+  auto h = [](uint32_t v) { return __half2float(__ushort_as_half((unsigned short)v)); };
+  return trilerp8(h(p0.x & 0xFFFFu), h(p0.x >> 16), h(p0.y & 0xFFFFu), h(p0.y >> 16),
+                  h(p1.x & 0xFFFFu), h(p1.x >> 16), h(p1.y & 0xFFFFu), h(p1.y >> 16), fx, fy, fz);
+}
+
+// The march kernels' density lookup: the quad copy when the volume has one.
+template <typename T>
+__device__ __forceinline__ float density_march(const T *__restrict__ vol, const BrickGrid &g,
+                                               const uint2 *__restrict__ q, const BrickGrid &qg,
+                                               f3 x) {
+  if constexpr (sizeof(T) == 2) {
+    if (q) return density_at_quad(q, qg, g, x);
+  }
+  return density_at(vol, g, x);
 }
 
 // Transfer function: 256 RGBA entries (float4) at density e/255, linear interpolation.

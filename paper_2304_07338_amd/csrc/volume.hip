@@ -26,6 +26,32 @@ hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, 
   return hipGetLastError();
 }
 
+// Quad copy of a binary16 volume: entry (a, b, k) of grid qg (sizes nx+1, ny+1, nz) holds the
+// values at (a-1, b-1), (a, b-1), (a-1, b), (a, b) of plane k, indices clamped to the volume.
+__global__ void quad_kernel(const unsigned short *__restrict__ vol, BrickGrid vg,
+                            uint2 *__restrict__ q, BrickGrid qg) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)qg.nx * qg.ny * qg.nz;
+  if (i >= n) return;
+  const int a = (int)(i % qg.nx);
+  const int b = (int)((i / qg.nx) % qg.ny);
+  const int k = (int)(i / ((size_t)qg.nx * qg.ny));
+  const int x0 = max(a - 1, 0), x1 = min(a, vg.nx - 1);
+  const int y0 = max(b - 1, 0), y1 = min(b, vg.ny - 1);
+  const int oz = brick_oz(vg, k);
+  auto v = [&](int x, int y) { return (uint32_t)vol[brick_ox(x) + brick_oy(vg, y) + oz]; };
+  q[brick_ox(a) + brick_oy(qg, b) + brick_oz(qg, k)] =
+      make_uint2(v(x0, y0) | (v(x1, y0) << 16), v(x0, y1) | (v(x1, y1) << 16));
+}
+
+hipError_t launch_quad_volume(pfn_context *ctx) {
+  const BrickGrid &qg = ctx->qvol_grid;
+  size_t n = (size_t)qg.nx * qg.ny * qg.nz;
+  hipLaunchKernelGGL(quad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                     (const unsigned short *)ctx->vol, ctx->vol_grid, ctx->qvol, qg);
+  return hipGetLastError();
+}
+
 struct LightVolArgs {
   const void *vol;
   BrickGrid vg, lvg;

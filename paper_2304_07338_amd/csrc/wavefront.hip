@@ -120,7 +120,7 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
       }
       float tt = t0 + (float)j * job.step + xi * l;
       f3 x = eye + d * tt;
-      float rho = density_at(reinterpret_cast<const VT *>(a.m.vol), a.m.vg, x);
+      float rho = density_march(reinterpret_cast<const VT *>(a.m.vol), a.m.vg, a.m.qvol, a.m.qg, x);
       float4 o = tf_lookup(tf, rho);
       float sig = o.w * a.m.ext_scale;
       float alpha = -expm1f(-sig * l);
