@@ -216,7 +216,7 @@ struct Tri {
   float fx, fy, fz;
 };
 __device__ __forceinline__ void tri_axis(float x, int n, int &i0, int &i1, float &f) {
-  float u = x * (float)n - 0.5f;
+  const float u = fmaf(x, (float)n, -0.5f);  // one rounding, whatever the calling kernel
   float fl = floorf(u);
   f = u - fl;
   int lo = (int)fl;

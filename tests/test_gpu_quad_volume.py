@@ -1,0 +1,84 @@
+"""The march kernels' density lookup for binary16 volumes reads a quad copy of the volume (each
+entry the four (x, y) corners of a cell, one 8-byte load per z plane).  It must read the same
+corners as the plain trilinear lookup: a binary16 volume and an FP32 volume holding the same
+(binary16-rounded) values give identical march-step and query counts and images that agree to
+FP32 rounding (the two kernels are compiled separately and may order a few FP32 operations
+differently; a wrong corner changes pixels by orders of magnitude more).  Covered: the fused
+kernel and the wavefront rounds, with a field and with the photon cache, for a brick-aligned
+and a ragged volume (the clamped corners at the faces of the cube are where the quad
+indexing differs from the plain one)."""
+import numpy as np
+import pytest
+
+from gpu_common import gpu_context, say, scene_arrays, smooth_cache
+from paper_2304_07338_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def _volume(shape, seed):
+    """Smooth random density in [0, 1] with sharp structure, [z][y][x]."""
+    import torch
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny,
+                          (np.arange(nx) + 0.5) / nx, indexing="ij")
+    v = 0.5 + 0.5 * np.sin(6.0 * x + rng.uniform(0, 6)) * np.cos(5.0 * y + rng.uniform(0, 6))
+    v = v * (0.6 + 0.4 * z) + 0.2 * rng.random(shape)
+    v = np.clip(v, 0.0, 1.0)
+    v16 = torch.tensor(v, dtype=torch.float16)
+    return v16, v16.float()
+
+
+def _setup(ctx, field_seed):
+    import torch
+    from paper_2304_07338_amd.pfn import FieldConfig
+    ctx.build_light_volume(0.5)
+    ctx.field_select(0)
+    ctx.field_init(FieldConfig(log2_table=14), seed=field_seed)
+    p = ctx.field_get_params()
+    g = torch.Generator(device="cuda:0").manual_seed(field_seed)
+    ctx.field_set_params((p + 0.3 * torch.rand(p.shape, device="cuda:0", generator=g) - 0.15)
+                         .contiguous())
+    ctx.field_set_kappa(1e-2)
+    ctx.set_cache(torch.tensor(smooth_cache(16, 2, seed=1), dtype=torch.float32, device="cuda:0"),
+                  [-0.5, 0.5], 1.0)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (21, 29, 37)])
+def test_binary16_volume_renders_as_its_fp32_values(shape):
+    from paper_2304_07338_amd.pfn import (DIRECT_LIGHT_VOLUME, DIRECT_SHADOW_RAYS, INDIRECT_CACHE,
+                                          INDIRECT_FIELD, RenderConfig)
+    w, _, tf, lights = scene_arrays("c0")
+    v16, v32 = _volume(shape, seed=sum(shape))
+    ctxs = {}
+    for name, v in (("f16", v16), ("f32", v32)):
+        ctxs[name] = gpu_context(v, tf, lights)
+        _setup(ctxs[name], field_seed=7)
+    # the view covers the whole cube, so rays cross every face
+    cam = sg.Camera((0.5, 0.55, -0.9), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), 60.0, 41, 33)
+    cases = [("fused", INDIRECT_FIELD, DIRECT_LIGHT_VOLUME), ("wavefront", INDIRECT_FIELD,
+             DIRECT_LIGHT_VOLUME), ("wavefront", INDIRECT_FIELD, DIRECT_SHADOW_RAYS),
+             ("fused", INDIRECT_CACHE, DIRECT_SHADOW_RAYS)]
+    for strategy, ind, direct in cases:
+        cfg = RenderConfig(spp=2, t_min=1e-3, max_steps=600, field_stride=2, g=0.3, indirect=ind,
+                           direct=direct, field_precision="f16", field_slot=0, seed=3)
+        out = {}
+        for name, ctx in ctxs.items():
+            ctx.set_render_strategy(strategy if ind == INDIRECT_FIELD else "fused")
+            ctx.count_enable(True)
+            img = ctx.render_frame(cam, cfg).cpu().numpy()
+            counts = tuple(ctx.count_get())
+            ctx.count_enable(False)
+            ctx.sync()
+            out[name] = (img, counts)
+        (a, ca), (b, cb) = out["f16"], out["f32"]
+        diff = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+        say(f"  {shape} {strategy} ind={ind} direct={direct}: counts {ca} / {cb}, "
+            f"mean {a.mean():.4g}, max diff / max {diff:.2e}")
+        assert a.mean() > 0
+        assert ca == cb
+        np.testing.assert_allclose(a, b, rtol=1e-6, atol=1e-6 * np.abs(b).max())
+    for ctx in ctxs.values():
+        ctx.set_render_strategy("auto")
+        ctx.close()
