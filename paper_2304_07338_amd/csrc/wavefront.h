@@ -98,8 +98,9 @@ __device__ __forceinline__ int find_job_ray(const MarchJob *jobs, int n_jobs, in
 // `feat_bytes` bytes; kept between frames and grown on demand.
 hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes);
 // Level groups of the position encoding of field slot `slot`: the coarse levels together (up to
-// WF_GROUP_BYTES of tables), each fine hashed level alone (the ray marcher then encodes
-// consecutive fine levels in one launch, each on its own XCDs).
+// WF_GROUP_BYTES of tables), each fine hashed level alone.  The Algorithm 2 renderer launches
+// these groups; the ray marcher pairs 8 to 16 levels over the XCDs in one launch and uses the
+// groups (consecutive fine levels merged, each on its own XCDs) only for other level counts.
 std::vector<std::pair<int, int>> wf_level_groups(const pfn_context *ctx, int slot,
                                                  const FieldDev &fd_host, size_t feat_bytes);
 // Field-kernel workgroups that are resident on the device at once.
