@@ -184,6 +184,7 @@ def main():
     march_ms, launches = ctx.timing_get(_ffi.TK_MARCH)
     ktimes = {k: ctx.timing_get(i) for k, i in (("wf_march_kernel", _ffi.TK_WF_MARCH),
                                                  ("wf_encode_kernel", _ffi.TK_WF_ENCODE),
+                                                 ("wf_dir_kernel", _ffi.TK_WF_DIR),
                                                  ("wf_field_kernel", _ffi.TK_WF_FIELD),
                                                  ("wf_resolve_kernel", _ffi.TK_WF_RESOLVE))}
     ctx.timing_enable(False)
@@ -203,10 +204,12 @@ def main():
     if ktimes["wf_march_kernel"][1] > 0:
         # wavefront form: per kernel, per frame
         # the position encoding reads a query's 16 x 8 grid corners and its position once and
-        # writes its 16 features (the launches that read the position again, and the direction
-        # launches timed with them, add no algorithmic bytes)
+        # writes its 16 features (the XCDs that read the position again add no algorithmic
+        # bytes); the direction encoding reads 16 x 4 corners and writes 16 features per ray
+        # of a round
         per = {"wf_march_kernel": (steps_f * step_bytes + queries_f * 24, 0),
                "wf_encode_kernel": (queries_f * (16 * 8 * feat_bytes + 16 * feat_bytes + 12), 0),
+               "wf_dir_kernel": (0, 0),
                "wf_field_kernel": (queries_f * (16 * feat_bytes + 12), queries_f * mlp_flop),
                "wf_resolve_kernel": (0, 0)}
         for k, (ms, n) in ktimes.items():
@@ -217,7 +220,7 @@ def main():
                           "GB_s": round(b / (kms * 1e-3) / 1e9, 2) if kms > 0 else None}
             if fl:
                 kernels[k]["TFLOP_s"] = round(fl / (kms * 1e-3) / 1e12, 3)
-        dom = max((k for k in kernels if k != "wf_resolve_kernel"),
+        dom = max((k for k in kernels if k not in ("wf_resolve_kernel", "wf_dir_kernel")),
                   key=lambda k: kernels[k]["ms_per_frame"])
         dom_bytes = kernels[dom]["algorithmic_bytes_per_frame"]
         dom_ms = kernels[dom]["ms_per_frame"]
@@ -323,7 +326,8 @@ def first_interaction_bench(ctx, cam, rc, args):
         wall = (time.perf_counter() - ts) * 1000.0 / n
         kms = {k: ctx.timing_get(i)[0] / n for k, i in (
             ("sample", _ffi.TK_FI_SAMPLE), ("nee", _ffi.TK_FI_NEE),
-            ("field_encode", _ffi.TK_WF_ENCODE), ("field_mlp", _ffi.TK_WF_FIELD),
+            ("field_encode", _ffi.TK_WF_ENCODE), ("field_dir", _ffi.TK_WF_DIR),
+            ("field_mlp", _ffi.TK_WF_FIELD),
             ("resolve", _ffi.TK_WF_RESOLVE), ("frame", _ffi.TK_MARCH))}
         ctx.timing_enable(False)
         mean = float(out.mean())
@@ -344,7 +348,8 @@ def first_interaction_bench(ctx, cam, rc, args):
                     "speedup_vs_path_tracer": round(pt_ms / wall, 3), "image_mean": mean}
         log(f"[alg2] {key}: {wall:.3f} ms/frame ({kms['frame']:.3f} ms GPU; sample "
             f"{kms['sample']:.3f}, NEE {kms['nee']:.3f}, field {kms['field_encode']:.3f} + "
-            f"{kms['field_mlp']:.3f}, resolve {kms['resolve']:.3f}), {inter} interactions; "
+            f"{kms['field_dir']:.3f} + {kms['field_mlp']:.3f}, resolve {kms['resolve']:.3f}), "
+            f"{inter} interactions; "
             f"path tracer (16 collisions) {pt_ms:.3f} ms")
     return {"workload": "c2 scene, Algorithm 2 renderer, 1 spp, f16 field",
             "g": rc.g, "indirect": "field", "per_resolution": res,

@@ -355,7 +355,8 @@ pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs,
  * 8 = matrix-core field tiles, 9 = pixel resolve (the first-interaction renderer also reports
  * its field pass under 7 and 8 and its resolve under 9); first-interaction renderer:
  * 10 = ray generation, delta-tracking sampling and compaction, 11 = next-event estimation;
- * 12 = photon-map estimate.
+ * 12 = photon-map estimate; 13 = view-direction encoding of the wavefront and first-interaction
+ * field passes.
  * Ids 0..15 are valid. */
 pfn_status pfn_timing_enable(pfn_context *ctx, int on);
 pfn_status pfn_timing_get(pfn_context *ctx, int kernel, double *host_ms, int64_t *host_launches);

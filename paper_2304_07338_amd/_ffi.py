@@ -16,7 +16,7 @@ INDIRECT_NONE, INDIRECT_CACHE, INDIRECT_FIELD = 0, 1, 2
 DIRECT_SHADOW_RAYS, DIRECT_LIGHT_VOLUME = 0, 1
 TK_MARCH, TK_TRACE, TK_TRAIN, TK_PT, TK_QUERY, TK_ADAM = 0, 1, 2, 3, 4, 5
 TK_WF_MARCH, TK_WF_ENCODE, TK_WF_FIELD, TK_WF_RESOLVE = 6, 7, 8, 9
-TK_FI_SAMPLE, TK_FI_NEE, TK_PM_ESTIMATE = 10, 11, 12
+TK_FI_SAMPLE, TK_FI_NEE, TK_PM_ESTIMATE, TK_WF_DIR = 10, 11, 12, 13
 
 
 class PointLight(C.Structure):

@@ -200,7 +200,7 @@ struct pfn_context {
 enum TimedKernel {
   TK_MARCH = 0, TK_TRACE = 1, TK_TRAIN = 2, TK_PT = 3, TK_QUERY = 4, TK_ADAM = 5,
   TK_WF_MARCH = 6, TK_WF_ENCODE = 7, TK_WF_FIELD = 8, TK_WF_RESOLVE = 9, TK_FI_SAMPLE = 10,
-  TK_FI_NEE = 11, TK_PM_ESTIMATE = 12
+  TK_FI_NEE = 11, TK_PM_ESTIMATE = 12, TK_WF_DIR = 13
 };
 
 // Error helpers

@@ -108,8 +108,9 @@ int wf_field_blocks(int prec, int mlp_bytes);
 // The encoding launches (one per level group), the direction encoding and the field kernel of
 // one round, on stream st.
 // split_levels: each group launch runs one thread per (level, query) instead of one per query.
-// field_st: when set, the field kernel runs on that stream instead, after enc_done (recorded on
-// st once the encodings are done).
+// field_st: when set, the direction encoding and the field kernel run on that stream instead
+// (which the caller has made wait for the march kernel), the field kernel after enc_done
+// (recorded on st once the position encodings are done).
 hipError_t wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, const WfEncArgs &e,
                                 const WfDirArgs &dg,
                                 const std::vector<std::pair<int, int>> &groups,

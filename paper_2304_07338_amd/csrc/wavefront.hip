@@ -588,6 +588,15 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
                              const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
                              const WfFieldArgs &f, int field_blocks, bool split_levels,
                              hipStream_t fst, hipEvent_t enc_done) {
+  // the direction encoding only needs the march kernel's outputs: with a field stream it runs
+  // there, beside the position encodings
+  {
+    hipStream_t ds = fst ? fst : st;
+    const int ts = timing_begin_on(ctx, ds);
+    hipLaunchKernelGGL((wf_dir_kernel<P>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
+                       dim3(WF_THREADS), 0, ds, dg);
+    timing_end_on(ctx, ts, TK_WF_DIR, ds);
+  }
   const int64_t threads = (((int64_t)e.n_entries + 63) >> 6) << (6 + e.kshift);
   for (auto &g : groups) {
     WfEncArgs ee = e;
@@ -612,12 +621,6 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
     }
     const int ts = timing_begin_on(ctx, st);
     hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
-    timing_end_on(ctx, ts, TK_WF_ENCODE, st);
-  }
-  {
-    const int ts = timing_begin_on(ctx, st);
-    hipLaunchKernelGGL((wf_dir_kernel<P>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
-                       dim3(WF_THREADS), 0, st, dg);
     timing_end_on(ctx, ts, TK_WF_ENCODE, st);
   }
   if (fst) {
@@ -857,7 +860,10 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     f.in_ci = w.list_ci[cur];
     f.out_ci = w.list_ci[cur ^ 1];
     const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));
-    if (overlap) PFN_HIP(ctx, hipStreamWaitEvent(sb, w.ev_march[p], 0));
+    if (overlap) {
+      PFN_HIP(ctx, hipStreamWaitEvent(sb, w.ev_march[p], 0));
+      PFN_HIP(ctx, hipStreamWaitEvent(sc, w.ev_march[p], 0));
+    }
     PFN_HIP(ctx, wf_launch_field_pass(ctx, sb, prec, e, dg, groups, f, fb, false,
                                       overlap ? w.side2 : nullptr, w.ev_enc[p]));
     PFN_HIP(ctx, hipGetLastError());
