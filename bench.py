@@ -89,8 +89,8 @@ def main():
     ap.add_argument("--st-photons", type=int, default=22, help="log2 photons per study trace")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the renderer runs on one GPU; --gpus {args.gpus} is not supported "
+              "(sharding over several GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.matched_rmse:
