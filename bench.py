@@ -209,15 +209,16 @@ def main():
         # of a round
         per = {"wf_march_kernel": (steps_f * step_bytes + queries_f * 24, 0),
                "wf_encode_kernel": (queries_f * (16 * 8 * feat_bytes + 16 * feat_bytes + 12), 0),
-               "wf_dir_kernel": (0, 0),
+               "wf_dir_kernel": (None, 0),  # per ray of a round; rays per round not counted
                "wf_field_kernel": (queries_f * (16 * feat_bytes + 12), queries_f * mlp_flop),
                "wf_resolve_kernel": (0, 0)}
         for k, (ms, n) in ktimes.items():
             kms = ms / args.steps
             b, fl = per[k]
             kernels[k] = {"ms_per_frame": round(kms, 4), "launches_per_frame": n / args.steps,
-                          "algorithmic_bytes_per_frame": int(b),
-                          "GB_s": round(b / (kms * 1e-3) / 1e9, 2) if kms > 0 else None}
+                          "algorithmic_bytes_per_frame": None if b is None else int(b),
+                          "GB_s": round(b / (kms * 1e-3) / 1e9, 2)
+                          if b is not None and kms > 0 else None}
             if fl:
                 kernels[k]["TFLOP_s"] = round(fl / (kms * 1e-3) / 1e12, 3)
         dom = max((k for k in kernels if k not in ("wf_resolve_kernel", "wf_dir_kernel")),
