@@ -58,7 +58,12 @@ pfn_status pfn_set_stream(pfn_context *ctx, void *hip_stream);
 
 /* ------------------------------------------------------------------ scene */
 /* Scalar volume (Algorithm 1: Volume(x,y,z)): dev_density holds nx*ny*nz values of `dtype`
- * (PFN_F32 or PFN_F16) in [0,1], copied into a context-owned brick layout.  Sizes 2..4096. */
+ * (PFN_F32 or PFN_F16) in [0,1], x fastest, copied into a context-owned brick layout.  A
+ * PFN_F16 volume also gets a context-owned copy holding the four (x, y) corners of every cell
+ * (8 bytes per cell, about 4x the volume: 1.1 GB at 512^3) for the ray marcher's density
+ * lookups.  Sizes 2..4096, with fewer than 2^31 brick elements (PFN_ERR_INVALID_ARG
+ * otherwise).  dev_density is read by a kernel enqueued on the context's stream: it must stay
+ * valid until that work has run (stream order). */
 pfn_status pfn_set_volume(pfn_context *ctx, const void *dev_density, pfn_dtype dtype, int nx,
                           int ny, int nz);
 /* Transfer function (Algorithm 1: TransferFunction(sample)): 256 RGBA entries sampled at
