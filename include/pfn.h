@@ -79,7 +79,9 @@ typedef struct {
 pfn_status pfn_set_lights(pfn_context *ctx, const pfn_point_light *host_lights, int n_lights);
 /* Light-transmittance grid for direct light (one channel per light) at half the volume
  * resolution per axis, each value the exact shadow-march transmittance from the grid point to
- * the light with `step_voxels` steps (global shadows, Section 4.3). */
+ * the light with `step_voxels` steps (global shadows, Section 4.3).  With at most 3 lights a
+ * context-owned copy holding the four (x, y) corner texels of every cell (24 bytes per cell)
+ * is also built, for the ray marcher's lookups. */
 pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels);
 
 /* ------------------------------------------------------------------ 1. photon cache */

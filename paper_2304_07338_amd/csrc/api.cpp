@@ -140,6 +140,7 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   dev_free(ctx->qvol);
   dev_free(ctx->tf_dev);
   dev_free(ctx->lightvol);
+  dev_free(ctx->lquad);
   dev_free(ctx->cache);
   dev_free(ctx->rec_x);
   dev_free(ctx->rec_w);
@@ -302,6 +303,22 @@ extern "C" pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels
   ctx->lv_elems = elems;
   PFN_HIP(ctx, hipMemsetAsync(ctx->lightvol, 0, elems * sizeof(ushort4), ctx->stream));
   PFN_HIP(ctx, launch_light_volume(ctx, step_voxels / (float)ctx->nmax));
+  ctx->lquad_lights = 0;
+  if (ctx->n_lights <= 3) {
+    // the march kernels' four-load light lookups (24 bytes per cell)
+    size_t qe = 0;
+    const BrickGrid qg = make_brick_grid(g.nx + 1, g.ny + 1, g.nz, &qe);
+    if (!ctx->lquad || ctx->lquad_elems < qe) {
+      dev_free(ctx->lquad);
+      ctx->lquad = nullptr;
+      ctx->lquad_elems = 0;
+      PFN_HIP(ctx, dev_alloc((void **)&ctx->lquad, qe * 6 * sizeof(uint32_t)));
+      ctx->lquad_elems = qe;
+    }
+    ctx->lquad_grid = qg;
+    PFN_HIP(ctx, launch_light_quad(ctx));
+    ctx->lquad_lights = ctx->n_lights;
+  }
   ctx->lv_valid = true;
   return PFN_OK;
 }
@@ -698,6 +715,10 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
     }
   a.lightvol = ctx->lightvol;
   a.lvg = ctx->lv_grid;
+  a.lquad = ctx->lv_valid && ctx->lquad_lights > 0 && ctx->lquad_lights == ctx->n_lights
+                ? ctx->lquad
+                : nullptr;
+  a.lqg = ctx->lquad_grid;
   a.cache = ctx->cache;
   a.cache_res = ctx->cache_res;
   a.fields = ctx->fields_dev;

@@ -37,6 +37,8 @@ struct MarchArgs {
   float light_pos[PFN_MAX_LIGHTS][3], light_int[PFN_MAX_LIGHTS][3];
   const ushort4 *lightvol;
   BrickGrid lvg;
+  const uint32_t *lquad;  // up to 3 lights: quad copy of the light volume (else null)
+  BrickGrid lqg;
   const float4 *cache;
   int cache_res;
   const FieldDev *fields;        // per field slot

@@ -27,6 +27,41 @@ __device__ __forceinline__ float4 tri_fetch4(const ushort4 *__restrict__ p, cons
   return acc;
 }
 
+// tri_fetch4 for up to 3 lights from the quad copy of the light volume (grid qg over the light
+// grid g): per z plane one 24-byte entry holds channels 0-2 of the four (x, y) corner texels.
+// Same corners, weights and sums as tri_fetch4; channel 3 is 0.
+__device__ __forceinline__ float4 tri_fetch4_quad(const uint32_t *__restrict__ q,
+                                                  const BrickGrid &qg, const BrickGrid &g, f3 x) {
+  int i0, i1, j0, j1, k0, k1;
+  float fx, fy, fz;
+  tri_axis(x.x, g.nx, i0, i1, fx);
+  tri_axis(x.y, g.ny, j0, j1, fy);
+  tri_axis(x.z, g.nz, k0, k1, fz);
+  const int64_t oxy = (int64_t)brick_ox(quad_axis(i0, i1, g.nx)) + brick_oy(qg, quad_axis(j0, j1, g.ny));
+  const uint32_t *p0 = q + 6 * (oxy + brick_oz(qg, k0)), *p1 = q + 6 * (oxy + brick_oz(qg, k1));
+  float gx = 1.0f - fx, gy = 1.0f - fy, gz = 1.0f - fz;
+  const float w[8] = {gx * gy * gz,   fx * gy * gz,   gx * fy * gz,   fx * fy * gz,
+                      gx * gy * fz,   fx * gy * fz,   gx * fy * fz,   fx * fy * fz};
+  uint32_t d[12];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    d[i] = p0[i];
+    d[6 + i] = p1[i];
+  }
+  auto h = [&](int e) {  // binary16 value e of the 24 (texel e / 3, channel e % 3)
+    const uint32_t v = d[e >> 1];
+    return __half2float(__ushort_as_half((unsigned short)((e & 1) ? (v >> 16) : (v & 0xFFFFu))));
+  };
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    acc.x = fmaf(w[k], h(3 * k), acc.x);
+    acc.y = fmaf(w[k], h(3 * k + 1), acc.y);
+    acc.z = fmaf(w[k], h(3 * k + 2), acc.z);
+  }
+  return acc;
+}
+
 template <typename VT>
 __device__ __forceinline__ float sigma_at(const MarchArgs &a, const float4 *tf, f3 x) {
   float rho = density_march(reinterpret_cast<const VT *>(a.vol), a.vg, a.qvol, a.qg, x);
@@ -59,7 +94,9 @@ __device__ __forceinline__ f3 direct_light(const MarchArgs &a, const MarchJob &j
                                            const float4 *tf, f3 x, f3 wo) {
   f3 Ld = {0.0f, 0.0f, 0.0f};
   float4 tl = make_float4(1.f, 1.f, 1.f, 1.f);
-  if constexpr (DIRECT == PFN_DIRECT_LIGHT_VOLUME) tl = tri_fetch4(a.lightvol, tri_setup(a.lvg, x));
+  if constexpr (DIRECT == PFN_DIRECT_LIGHT_VOLUME)
+    tl = a.lquad ? tri_fetch4_quad(a.lquad, a.lqg, a.lvg, x)
+                 : tri_fetch4(a.lightvol, tri_setup(a.lvg, x));
   // HG phase (1 - g^2) / (4 pi) * d^(-3/2), d = 1 + g^2 - 2 g mu, and the inverse-square falloff,
   // all through reciprocal square roots (no divisions in the step loop)
   const float g = job.g;

@@ -137,6 +137,10 @@ struct pfn_context {
   ushort4 *lightvol = nullptr;
   BrickGrid lv_grid{};
   size_t lv_elems = 0;
+  uint32_t *lquad = nullptr;   // up to 3 lights: channels 0-2 of the four (x, y) corner texels
+  BrickGrid lquad_grid{};      // of every light-volume cell (6 dwords), for four-load lookups
+  size_t lquad_elems = 0;
+  int lquad_lights = 0;        // lights the copy was built for (0: none)
   bool lv_valid = false;
 
   // photon cache: float4 (RGB, pad) per cell, [bins][res^3] x fastest
@@ -223,6 +227,7 @@ void timing_end_on(pfn_context *ctx, int slot, int kernel, hipStream_t stream);
 
 // Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
 hipError_t launch_quad_volume(pfn_context *ctx);
+hipError_t launch_light_quad(pfn_context *ctx);
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
                                int nz);
 hipError_t launch_light_volume(pfn_context *ctx, float step);

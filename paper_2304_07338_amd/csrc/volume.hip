@@ -124,3 +124,39 @@ hipError_t launch_light_volume(pfn_context *ctx, float step) {
     hipLaunchKernelGGL(light_volume_kernel<float>, dim3(blocks), dim3(256), 0, ctx->stream, a);
   return hipGetLastError();
 }
+
+// Quad copy of the light volume for up to 3 lights: entry (a, b, k) of grid qg (sizes nx+1,
+// ny+1, nz of the light grid) holds channels 0-2 of the texels at (a-1, b-1), (a, b-1),
+// (a-1, b), (a, b) of plane k (indices clamped), 12 binary16 values in 6 dwords.
+__global__ void light_quad_kernel(const ushort4 *__restrict__ lv, BrickGrid g,
+                                  uint32_t *__restrict__ q, BrickGrid qg) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)qg.nx * qg.ny * qg.nz;
+  if (i >= n) return;
+  const int a = (int)(i % qg.nx);
+  const int b = (int)((i / qg.nx) % qg.ny);
+  const int k = (int)(i / ((size_t)qg.nx * qg.ny));
+  const int x0 = max(a - 1, 0), x1 = min(a, g.nx - 1);
+  const int y0 = max(b - 1, 0), y1 = min(b, g.ny - 1);
+  const int oz = brick_oz(g, k);
+  const ushort4 t00 = lv[brick_ox(x0) + brick_oy(g, y0) + oz];
+  const ushort4 t10 = lv[brick_ox(x1) + brick_oy(g, y0) + oz];
+  const ushort4 t01 = lv[brick_ox(x0) + brick_oy(g, y1) + oz];
+  const ushort4 t11 = lv[brick_ox(x1) + brick_oy(g, y1) + oz];
+  uint32_t *o = q + 6 * (size_t)(brick_ox(a) + brick_oy(qg, b) + brick_oz(qg, k));
+  auto w = [](unsigned short lo, unsigned short hi) { return (uint32_t)lo | ((uint32_t)hi << 16); };
+  o[0] = w(t00.x, t00.y);
+  o[1] = w(t00.z, t10.x);
+  o[2] = w(t10.y, t10.z);
+  o[3] = w(t01.x, t01.y);
+  o[4] = w(t01.z, t11.x);
+  o[5] = w(t11.y, t11.z);
+}
+
+hipError_t launch_light_quad(pfn_context *ctx) {
+  const BrickGrid &qg = ctx->lquad_grid;
+  size_t n = (size_t)qg.nx * qg.ny * qg.nz;
+  hipLaunchKernelGGL(light_quad_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     ctx->stream, ctx->lightvol, ctx->lv_grid, ctx->lquad, qg);
+  return hipGetLastError();
+}
