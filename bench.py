@@ -629,9 +629,10 @@ def matched_rmse(args):
     }
 
 
-def ssim(img, ref):
-    """Mean SSIM (Gaussian window sigma 1.5, K1 = 0.01, K2 = 0.03) of the luminance (RGB mean)
-    of two images, with the reference's maximum as the dynamic range."""
+def ssim_map(img, ref):
+    """Per-pixel SSIM (Wang et al. 2004: Gaussian window sigma 1.5 truncated at 3.5 sigma,
+    K1 = 0.01, K2 = 0.03) of the luminance (RGB mean) of two images, with the reference's
+    maximum as the dynamic range L; borders are reflected."""
     import numpy as np
     from scipy.ndimage import gaussian_filter
     a = np.asarray(img, dtype=np.float64).mean(-1)
@@ -641,8 +642,12 @@ def ssim(img, ref):
     f = lambda x: gaussian_filter(x, 1.5, truncate=3.5)
     ma, mb = f(a), f(b)
     va, vb, cab = f(a * a) - ma * ma, f(b * b) - mb * mb, f(a * b) - ma * mb
-    m = ((2 * ma * mb + c1) * (2 * cab + c2)) / ((ma * ma + mb * mb + c1) * (va + vb + c2))
-    return float(m.mean())
+    return ((2 * ma * mb + c1) * (2 * cab + c2)) / ((ma * ma + mb * mb + c1) * (va + vb + c2))
+
+
+def ssim(img, ref):
+    """Mean SSIM over the image (ssim_map)."""
+    return float(ssim_map(img, ref).mean())
 
 
 def studies(args):

@@ -226,6 +226,13 @@ pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *params,
  * Section 3.5.2 and Table 1, or the final radius); host only, no context, no GPU.  Returns
  * PFN_ERR_INVALID_ARG for NULL pointers, steps < 1 or step outside [0, steps). */
 pfn_status pfn_train_step_radius(const pfn_train_params *params, int step, float *host_radius);
+/* The learning rate that pfn_train_field applies at `step` (Section 3.5.1): lr until
+ * decay_start, then lr * decay^(1 + floor((step - decay_start) / decay_interval)); with the
+ * defaults (9e-4, 0.92, 1400, 25 over 2000 steps) the rate drops at 70 % of the run and every
+ * 25 steps after.  Evaluated in FP64 and rounded to FP32 once, as the Adam launch receives it.
+ * Host only, no context, no GPU.  Returns PFN_ERR_INVALID_ARG for NULL pointers, steps < 1,
+ * step outside [0, steps), decay_interval < 1 or decay_start < 0. */
+pfn_status pfn_train_lr_at(const pfn_train_params *params, int step, float *host_lr);
 /* The training-batch generator alone (for checking): step `step`'s n samples. */
 pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
                            float *dev_xyz, float *dev_dir, float *dev_g, int32_t *dev_bin,

@@ -105,6 +105,7 @@ SIGNATURES = {
                                                vp]),
     "pfn_photon_map_build": (C.c_int, [ctxp, C.c_int]),
     "pfn_train_step_radius": (C.c_int, [C.POINTER(TrainParams), C.c_int, C.POINTER(C.c_float)]),
+    "pfn_train_lr_at": (C.c_int, [C.POINTER(TrainParams), C.c_int, C.POINTER(C.c_float)]),
     "pfn_photon_map_set": (C.c_int, [ctxp, vp, vp, vp, vp, C.c_uint64, C.c_int,
                                      C.POINTER(C.c_float), C.c_int]),
     "pfn_photon_map_get": (C.c_int, [ctxp, vp, C.c_size_t, vp, vp, vp, C.c_uint64,

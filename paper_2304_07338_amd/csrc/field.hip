@@ -244,7 +244,7 @@ __global__ __launch_bounds__(QUERY_THREADS) void field_query_kernel(
         w = {dir[3 * qi], dir[3 * qi + 1], dir[3 * qi + 2]};
         gg = g[qi];
       }
-      double u0, u1;
+      float u0, u1;
       dir_coords(w, u0, u1);
       f32x4 out = field_tile16<P>(F, lds_w, x, u0, u1, gg, valid);
       if (lane < 16 && valid) {

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_sample_kernel(FiArgs a) {
     float t0, t1;
     if (pixel_ok) {
       const f3 d = fi_ray_dir(job, px, py);
-      dir_coords_f(d * -1.0f, u0, u1);
+      dir_coords(d * -1.0f, u0, u1);
       const f3 eye = {job.eye[0], job.eye[1], job.eye[2]};
       if (clip_cube(eye, d, t0, t1) && a.majorant > 0.0f) {
         const uint64_t pix = (uint64_t)py * (uint64_t)job.width + (uint64_t)px;

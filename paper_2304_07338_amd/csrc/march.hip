@@ -30,7 +30,7 @@ __device__ f3 field_eval_wave(const FieldDev &F, const void *lds_w, f3 xq, float
     f3 x = {__shfl(xq.x, src), __shfl(xq.y, src), __shfl(xq.z, src)};
     float a0 = __shfl(u0, src), a1 = __shfl(u1, src);
     bool v = (vm >> src) & 1ull;
-    f32x4 out = field_tile16<P>(F, lds_w, x, (double)a0, (double)a1, g, v);
+    f32x4 out = field_tile16<P>(F, lds_w, x, a0, a1, g, v);
     float o0 = __shfl(out[0], lane & 15), o1 = __shfl(out[1], lane & 15),
           o2 = __shfl(out[2], lane & 15);
     if ((lane >> 4) == j) {
@@ -141,7 +141,7 @@ __device__ __forceinline__ void march_block(const MarchArgs &a, const MarchJob &
       j = 0;
       T = 1.0f;
       Cs = {0.f, 0.f, 0.f};
-      if constexpr (IND == PFN_INDIRECT_FIELD) dir_coords_f(wo, u0, u1);
+      if constexpr (IND == PFN_INDIRECT_FIELD) dir_coords(wo, u0, u1);
       live = n > 0;
     }
     if constexpr (IND == PFN_INDIRECT_FIELD) {

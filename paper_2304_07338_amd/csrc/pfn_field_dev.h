@@ -141,24 +141,15 @@ __device__ __forceinline__ float2 encode_pos_level(const FieldDev &F, int lv, f3
   return acc;
 }
 
-// Cell and fraction on a direction level from a double-precision coordinate: the finest levels
-// have N ~ 7000 cells, so the coordinate is kept in FP64 until the fraction is formed.
-__device__ __forceinline__ void level_cell_d(double u, int N, int &c, float &f) {
-  double y = u * (double)N;
-  double fl = fmin(floor(y), (double)(N - 1));
-  c = (int)fl;
-  f = (float)(y - fl);
-}
-
 template <int P>
-__device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, double u0, double u1) {
+__device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, float u0, float u1) {
   int N = F.dir.res[lv];
   uint32_t off = F.dir.off[lv];
   bool dense = (F.dir.dense_mask >> lv) & 1u;
   int cx, cy;
   float fx, fy;
-  level_cell_d(u0, N, cx, fx);
-  level_cell_d(u1, N, cy, fy);
+  level_cell(u0, N, cx, fx);
+  level_cell(u1, N, cy, fy);
   float2 acc = make_float2(0.0f, 0.0f);
   uint32_t s1 = (uint32_t)(N + 1);
   const bool pair_ok = (F.pair_ok & 2u) != 0u;
@@ -179,17 +170,13 @@ __device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, do
   return acc;
 }
 
-// Normalised spherical coordinates (theta/pi, (phi+pi)/(2pi)) of a unit direction, in FP64
-// (one evaluation per query; FP32 acos/atan2 rounding would be magnified by the fine levels).
-__device__ __forceinline__ void dir_coords(f3 w, double &u0, double &u1) {
-  const double pi = 3.14159265358979323846;
-  double z = fmin(1.0, fmax(-1.0, (double)w.z));
-  u0 = fmin(1.0, fmax(0.0, acos(z) / pi));
-  u1 = fmin(1.0, fmax(0.0, (atan2((double)w.y, (double)w.x) + pi) / (2.0 * pi)));
-}
-
-// FP32 variant for the renderer, whose view directions are themselves FP32 ray directions.
-__device__ __forceinline__ void dir_coords_f(f3 w, float &u0, float &u1) {
+// Normalised spherical coordinates (theta/pi, (phi+pi)/(2pi)) of a unit direction, in FP32.
+// The cell and fraction on a direction level then come from level_cell's single-rounding
+// split.  An error of a few ulps in the coordinate (acosf, atan2f and the scaling each round
+// once) moves the fraction of a level with N cells by N times that error, about 5e-4 on the
+// finest level of the standard field (N = 7006): the encoding itself is that sensitive to the
+// direction, whose FP32 components carry the same relative rounding.
+__device__ __forceinline__ void dir_coords(f3 w, float &u0, float &u1) {
   float z = fminf(1.0f, fmaxf(-1.0f, w.z));
   u0 = fminf(1.0f, fmaxf(0.0f, acosf(z) * (1.0f / PFN_PI)));
   u1 = fminf(1.0f, fmaxf(0.0f, (atan2f(w.y, w.x) + PFN_PI) * (0.5f / PFN_PI)));
@@ -203,7 +190,7 @@ __device__ __forceinline__ f3 clamp01(f3 x) {
 // The 16 encoder outputs of this lane for one query: pos[0..7] = position levels 4q..4q+3
 // (2 features each), dir[0..7] = direction levels 4q..4q+3.  Levels >= F.levels give 0.
 template <int P>
-__device__ __forceinline__ void encode_lane(const FieldDev &F, int q, f3 x, double u0, double u1,
+__device__ __forceinline__ void encode_lane(const FieldDev &F, int q, f3 x, float u0, float u1,
                                             bool valid, float pos[8], float dir[8]) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -381,7 +368,7 @@ __device__ __forceinline__ f32x4 mlp_forward16_f32(const float *__restrict__ w, 
 // MLP.  Returns the output tile (lanes 0..15: L' of query l).
 template <int P>
 __device__ __forceinline__ f32x4 field_tile16(const FieldDev &F, const void *__restrict__ lds_w,
-                                              f3 x, double u0, double u1, float g, bool valid) {
+                                              f3 x, float u0, float u1, float g, bool valid) {
   const int q = lane_id() >> 4;
   float pos[8], dir[8];
   encode_lane<P>(F, q, clamp01(x), u0, u1, valid, pos, dir);

@@ -239,8 +239,8 @@ struct ActT<P_F32> {
 };
 
 // Scatter the encoder-input gradients of this lane's 4 levels into the grid gradients.
-__device__ __forceinline__ void scatter_grid_grads(const TrainArgs &a, int q, f3 x, double u0,
-                                                   double u1, const float gp[8], const float gd[8]) {
+__device__ __forceinline__ void scatter_grid_grads(const TrainArgs &a, int q, f3 x, float u0,
+                                                   float u1, const float gp[8], const float gd[8]) {
   const FieldDev &F = a.F;
 #pragma unroll 1
   for (int j = 0; j < 4; ++j) {
@@ -274,8 +274,8 @@ __device__ __forceinline__ void scatter_grid_grads(const TrainArgs &a, int q, f3
       bool dense = (F.dir.dense_mask >> lv) & 1u;
       int cx, cy;
       float fx, fy;
-      level_cell_d(u0, N, cx, fx);
-      level_cell_d(u1, N, cy, fy);
+      level_cell(u0, N, cx, fx);
+      level_cell(u1, N, cy, fy);
       uint32_t s1 = (uint32_t)(N + 1);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
       }
     }
     x = clamp01(x);
-    double u0, u1;
+    float u0, u1;
     dir_coords(w, u0, u1);
     float pos[8], dir[8];
     encode_lane<P>(a.F, q, x, u0, u1, valid, pos, dir);
@@ -937,6 +937,23 @@ extern "C" pfn_status pfn_train_step_radius(const pfn_train_params *p, int step,
   return PFN_OK;
 }
 
+// Learning rate of step s (Section 3.5.1): constant, then decayed once at decay_start and once
+// more every decay_interval steps.
+static double step_lr(const pfn_train_params *p, int s) {
+  double lr = p->lr;
+  if (s >= p->decay_start)
+    lr *= std::pow((double)p->decay, (double)(1 + (s - p->decay_start) / p->decay_interval));
+  return lr;
+}
+
+extern "C" pfn_status pfn_train_lr_at(const pfn_train_params *p, int step, float *lr) {
+  if (!p || !lr || p->steps < 1 || step < 0 || step >= p->steps || p->decay_interval < 1 ||
+      p->decay_start < 0)
+    return PFN_ERR_INVALID_ARG;
+  *lr = (float)step_lr(p, step);
+  return PFN_OK;
+}
+
 extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *p, float *hist) {
   if (!ctx) return PFN_ERR_INVALID_ARG;
   if (!p) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "params are NULL");
@@ -1015,10 +1032,7 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
                   p->loss);
     }
     if (st) return st;
-    double lr = p->lr;
-    if (s >= p->decay_start)
-      lr *= std::pow((double)p->decay, (double)(1 + (s - p->decay_start) / p->decay_interval));
-    st = run_adam(ctx, f, f.grad, f.adam_t + 1, (float)lr, p->beta1, p->beta2, p->eps, scale, prec);
+    st = run_adam(ctx, f, f.grad, f.adam_t + 1, (float)step_lr(p, s), p->beta1, p->beta2, p->eps, scale, prec);
     if (st) return st;
     f.adam_t += 1;
   }

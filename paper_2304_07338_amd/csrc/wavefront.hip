@@ -101,7 +101,7 @@ __device__ __forceinline__ void march_entry(const WfArgs &a, const float4 *tf, c
       span = t1 - t0;
       float ns = ceilf(span / job.step);
       n = ns > (float)job.max_steps ? job.max_steps : (int)ns;
-      dir_coords_f(wo, u0, u1);
+      dir_coords(wo, u0, u1);
       live = n > j;
     }
   }
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
   const float2 u = e.ent_u[t];
   for (int lv = 0; lv < F.levels; ++lv)
     store_feat<P>(e.dfeat, (int64_t)lv * e.n_entries + t,
-                  encode_dir_level<P>(F, lv, (double)u.x, (double)u.y));
+                  encode_dir_level<P>(F, lv, u.x, u.y));
 }
 
 // Field kernel: a wave takes 16 neighbouring rays of the round (entries t0..t0+15, one per

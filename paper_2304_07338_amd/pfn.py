@@ -105,6 +105,17 @@ def train_step_radius(cfg: "TrainConfig", step: int) -> float:
     return r.value
 
 
+def train_lr_at(cfg: "TrainConfig", step: int) -> float:
+    """The learning rate that training applies at `step` (host only)."""
+    lib = _ffi.load()
+    r = C.c_float()
+    p = cfg.struct()
+    st = lib.pfn_train_lr_at(C.byref(p), step, C.byref(r))
+    if st != 0:
+        raise PfnError(st, "pfn_train_lr_at: bad arguments")
+    return r.value
+
+
 def camera_struct(cam) -> _ffi.CameraS:
     c = _ffi.CameraS()
     for i in range(3):

@@ -30,3 +30,39 @@ def test_out_of_range_step_is_rejected():
         train_step_radius(cfg, 10)
     with pytest.raises(PfnError):
         train_step_radius(cfg, -1)
+
+
+@pytest.mark.parametrize("step", [0, 1, 1399, 1400, 1424, 1425, 1426, 1449, 1450, 1999])
+def test_learning_rate_schedule_matches_oracle(orc, step):
+    """The rate pfn_train_field hands to Adam at `step` (Section 3.5.1: 9e-4, x0.92 from 70 % of
+    2000 steps and every 25 steps after) equals the oracle's schedule, rounded once to FP32."""
+    import numpy as np
+    from paper_2304_07338_amd.pfn import train_lr_at
+    cfg = TrainConfig()
+    got = train_lr_at(cfg, step)
+    # the parameter block carries lr and decay as FP32
+    ref = orc.lr_at(step, np.float32(cfg.lr), np.float32(cfg.decay), cfg.decay_start,
+                    cfg.decay_interval)
+    assert got == np.float32(ref), (step, got, ref)
+    closed = {0: 9e-4, 1399: 9e-4, 1400: 9e-4 * 0.92, 1424: 9e-4 * 0.92, 1425: 9e-4 * 0.92 ** 2,
+              1999: 9e-4 * 0.92 ** 24}
+    if step in closed:
+        assert got == pytest.approx(closed[step], rel=1e-6)
+
+
+def test_learning_rate_schedule_other_settings(orc):
+    import numpy as np
+    from paper_2304_07338_amd.pfn import train_lr_at
+    cfg = TrainConfig(steps=300, lr=1e-2, decay=0.5, decay_start=100, decay_interval=7)
+    for step in range(300):
+        ref = orc.lr_at(step, np.float32(cfg.lr), np.float32(cfg.decay), cfg.decay_start,
+                        cfg.decay_interval)
+        assert train_lr_at(cfg, step) == np.float32(ref), step
+
+
+def test_learning_rate_bad_arguments_are_rejected():
+    from paper_2304_07338_amd.pfn import train_lr_at
+    with pytest.raises(PfnError):
+        train_lr_at(TrainConfig(steps=10), 10)
+    with pytest.raises(PfnError):
+        train_lr_at(TrainConfig(steps=10, decay_interval=0), 3)
