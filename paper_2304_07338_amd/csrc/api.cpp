@@ -18,6 +18,10 @@ pfn_status pfn_fail(pfn_context *ctx, pfn_status st, const std::string &msg) {
 }
 
 pfn_status pfn_hip(pfn_context *ctx, hipError_t e, const char *what) {
+  // The runtime also keeps a failed call's status as its "last error"; clear it, so that the
+  // launch checks of later calls (hipGetLastError after a kernel launch) do not report it
+  // again.  A sticky device error is reported again by the runtime's next call anyway.
+  (void)hipGetLastError();
   std::string m = std::string(what) + ": " + hipGetErrorString(e);
   if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
     return pfn_fail(ctx, PFN_ERR_OUT_OF_MEMORY, m);

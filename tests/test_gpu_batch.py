@@ -4,7 +4,7 @@ rendering each job alone, and checked against the FP64 oracle."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -117,9 +117,9 @@ def test_batch_job_matches_oracle(orc, bctx):
                                g=cfgs[i].g, indirect=orc.IND_FIELD, direct=orc.DIR_LIGHTVOL,
                                light_mask=cfgs[i].light_mask, seed=cfgs[i].seed)
         ref = orc.render_pixels(os_, cams[i], op, field=(desc, p, 1, 1e-2))
-        err = rel_rmse(outs[i].cpu().numpy().reshape(-1, 3), ref)
-        say(f"  job {i} ({cams[i].width}x{cams[i].height}, spp {cfgs[i].spp}) rel-RMSE vs oracle {err:.2e}")
-        assert err < 3e-2
+        # binary16 light volume and field features; measured 1.2e-4 / 1.8e-4
+        check_err(outs[i].cpu().numpy().reshape(-1, 3), ref, 1.5e-3, 2e-3,
+                  f"job {i} ({cams[i].width}x{cams[i].height}, spp {cfgs[i].spp})")
 
 
 def test_autotuner_picks_a_config_and_keeps_results_exact(bctx):

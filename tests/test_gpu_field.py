@@ -3,7 +3,8 @@ oracle, and of a field-lit render."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import (check_err, coord_sensitivity, gpu_context, oracle_scene, rel_rmse, say,
+                        scene_arrays)
 
 pytestmark = pytest.mark.gpu
 
@@ -73,19 +74,29 @@ def test_field_query_parity_all_precisions(orc, fctx, levels, hidden, log2_table
     fctx.sync()
     ref = orc.field_forward(desc, pd, x, w, g, rounding=0)
     d = np.abs(lp.cpu().numpy() - ref)
-    say("  f32 max|dL'|", d.max(), "rms", np.sqrt((d ** 2).mean()), "|ref| rms", np.sqrt((ref ** 2).mean()))
-    assert d.max() <= 2e-5
+    # Per query: twice the oracle's own change when a direction coordinate moves by the FP32
+    # coordinate error, plus 2e-6 for FP32 accumulation in the MLP (measured 6e-7 with exact
+    # coordinates).
+    sens = coord_sensitivity(lambda dd: orc.field_forward(desc, pd, x, dd, g, rounding=0), w)
+    bar = 2.0 * sens + 2e-6
+    say("  f32 max|dL'|", d.max(), "rms", np.sqrt((d ** 2).mean()), "|ref| rms",
+        np.sqrt((ref ** 2).mean()), "max d/bar", (d / bar).max(), "median sens", np.median(sens))
+    assert np.all(d <= bar)
     dec = 2e-3 * 10.0 ** (-5.0 * ref)
     assert rel_rmse(rgb.cpu().numpy(), dec) <= 1e-4
     # 16-bit paths against the oracle with parameters rounded the same way
-    for prec, rounding, tol in (("f16", 1, 1e-3), ("bf16", 2, 8e-3)):
+    # bars: about 10x the largest measured over the three fields (f16 RMS 1.6e-5, max 6.9e-5;
+    # bf16 RMS 1.2e-4, max 4.7e-4), which come from activations that the GPU and the oracle
+    # round to 16 bits after differently ordered FP32 sums
+    for prec, rounding, tol_rms, tol_max in (("f16", 1, 1.5e-4, 6e-4), ("bf16", 2, 1.2e-3, 5e-3)):
         lp = fctx.field_query(dx, dw, dg, precision=prec, decode=False)
         fctx.sync()
         ref = orc.field_forward(desc, pd, x, w, g, rounding=rounding)
         d = lp.cpu().numpy() - ref
         rms = float(np.sqrt(np.mean(d ** 2)))
         say(f"  {prec} rms|dL'|", rms, "max", np.abs(d).max())
-        assert rms <= tol
+        assert rms <= tol_rms
+        assert np.abs(d).max() <= tol_max
 
 
 def test_field_query_empty_and_tiny(orc, fctx):
@@ -125,13 +136,14 @@ def test_render_with_field_parity(orc, strategy):
     ctx.field_set_kappa(5e-3)
     cam = sg.make_camera(w.seed, 4, 24, 20)
     os_ = oracle_scene(orc, vol, tf, lights)
-    for prec, rounding, tol in (("f32", 0, 2e-4), ("f16", 1, 2e-2), ("bf16", 2, 1.5e-1)):
+    # measured rel-RMSE / max: f32 7.4e-6 / 4.0e-6 (the FP32 direction coordinates), f16
+    # 1.3e-5 / 1.0e-5, bf16 7.4e-5 / 4.9e-5
+    for prec, rounding, tol, tol_max in (("f32", 0, 1e-4, 5e-5), ("f16", 1, 1.5e-4, 1e-4),
+                                         ("bf16", 2, 8e-4, 5e-4)):
         img = ctx.render_frame(cam, RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3,
                                                  field_precision=prec))
         ctx.sync()
         ref = orc.render_pixels(os_, cam, orc.render_params(indirect=orc.IND_FIELD, field_stride=4,
                                                             g=0.3),
                                 field=(desc, p.astype(np.float64), rounding, 5e-3))
-        err = rel_rmse(img.cpu().numpy().reshape(-1, 3), ref)
-        say(f"  {prec} rel-RMSE", err)
-        assert err <= tol
+        check_err(img.cpu().numpy().reshape(-1, 3), ref, tol, tol_max, prec)

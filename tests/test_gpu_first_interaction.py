@@ -2,22 +2,26 @@
 
 Both sides draw the same Philox numbers, so each delta-tracking walk takes the same decisions
 unless an FP32 and an FP64 comparison straddle a random number; such a flip changes a pixel
-wholesale.  The bar: at least 99 % of the pixels agree to the arithmetic's tolerance (FP32
-walk positions, cache gather or field evaluation; 3e-2 with binary16 field features), and the
-image means agree to 1 %.  Frames are deterministic although collisions are compacted with
+wholesale.  The bar: at least 99 % of the pixels agree to about 10x the measured 99th
+percentile of the per-pixel relative difference (2e-5 for the cache and direct light, measured
+2e-6; 1e-3 with an FP32 field, whose FP32 direction coordinates move L' by up to 2e-5 and the
+decoded radiance by psi ln 10 = 11.5 times that, measured 1.1e-4; 2e-3 with binary16 field
+features, measured 1.8e-4), and the image means agree to 1 %.  Frames are deterministic although collisions are compacted with
 atomics."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, say, scene_arrays, smooth_cache
+from gpu_common import gpu_context, oracle_scene, say, scene_arrays, smooth_cache, volume_as
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def fi(orc):
+@pytest.fixture(scope="module", params=["f32", "f16"])
+def fi(orc, request):
+    """The C0 volume as FP32 and as binary16 (the renderer's f16 instantiations)."""
     w, vol, tf, lights = scene_arrays("c0")
+    vol = volume_as(vol, request.param)
     ctx = gpu_context(vol, tf, lights)
     return dict(w=w, vol=vol, tf=tf, lights=lights, ctx=ctx,
                 os=oracle_scene(orc, vol, tf, lights))
@@ -40,8 +44,10 @@ def _agree(g, ref, rtol, what, min_frac=0.99):
     ok = np.all(np.abs(g - ref) <= rtol * np.abs(ref) + atol, axis=1)
     frac = ok.mean()
     mrel = abs(g.mean() / ref.mean() - 1.0)
+    q = (np.abs(g - ref) / (np.abs(ref) + atol)).max(axis=1)
     say(f"  {what}: {ok.sum()} / {ok.size} pixels agree (rtol {rtol}), mean {ref.mean():.4g}, "
-        f"mean rel diff {mrel:.2e}, nonzero {np.count_nonzero(ref.any(axis=1))}")
+        f"mean rel diff {mrel:.2e}, nonzero {np.count_nonzero(ref.any(axis=1))}, pixel rel diff "
+        f"p99 {np.quantile(q, 0.99):.2e} p99.9 {np.quantile(q, 0.999):.2e} max {q.max():.2e}")
     assert np.count_nonzero(ref.any(axis=1)) > 0.15 * ok.size
     assert frac >= min_frac
     assert mrel <= 1e-2
@@ -63,7 +69,7 @@ def test_cache_indirect_one_sample(orc, fi):
     fi["ctx"].sync()
     ref = orc.fi_pixels(fi["os"], cam, orc.fi_params(spp=1, g=0.3, indirect=orc.IND_CACHE,
                                                      seed=5), cache=oc)
-    _agree(img.cpu().numpy(), ref, 1e-4, "cache, 1 spp, 48x40")
+    _agree(img.cpu().numpy(), ref, 2e-5, "cache, 1 spp, 48x40")
 
 
 def test_direct_only_ragged_three_samples_and_light_mask(orc, fi):
@@ -73,10 +79,10 @@ def test_direct_only_ragged_three_samples_and_light_mask(orc, fi):
                                                            seed=6))
         fi["ctx"].sync()
         ref = orc.fi_pixels(fi["os"], cam, orc.fi_params(spp=3, g=-0.4, light_mask=mask, seed=6))
-        _agree(img.cpu().numpy(), ref, 1e-4, f"direct only, 3 spp, mask {mask}")
+        _agree(img.cpu().numpy(), ref, 2e-5, f"direct only, 3 spp, mask {mask}")
 
 
-@pytest.mark.parametrize("prec,rounding,rtol", [("f32", 0, 1e-4), ("f16", 1, 3e-2)])
+@pytest.mark.parametrize("prec,rounding,rtol", [("f32", 0, 1e-3), ("f16", 1, 2e-3)])
 def test_field_indirect_two_sample_groups(orc, fi, prec, rounding, rtol):
     """20 samples per pixel: two groups of 16 (a full tile and a partial one)."""
     import torch
@@ -113,7 +119,7 @@ def test_frame_of_two_chunks_sampled_and_deterministic(orc, fi):
     pix = np.sort(rng.choice(cam.width * cam.height, 4000, replace=False))
     ref = orc.fi_pixels(fi["os"], cam, orc.fi_params(spp=1, g=0.1, indirect=orc.IND_CACHE, seed=9),
                         pixels=pix, cache=oc)
-    _agree(a.reshape(-1, 3)[pix], ref, 1e-4, "1500x1440, 4000 sampled pixels")
+    _agree(a.reshape(-1, 3)[pix], ref, 2e-5, "1500x1440, 4000 sampled pixels")
     # with 8x8 tiles the rays from 2^21 on (the second chunk) are the pixels of rows >= 1392
     tail = pix[pix >= cam.width * 1392]
     assert tail.size > 50

@@ -4,7 +4,8 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, rel_rmse, say, scene_arrays, smooth_cache
+from gpu_common import (check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays,
+                        smooth_cache)
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -42,11 +43,9 @@ def test_c0_full_frame_cache_and_shadow_rays(orc, c0):
     cfg = RenderConfig(indirect=INDIRECT_CACHE, g=0.0)
     ocfg = orc.render_params(indirect=orc.IND_CACHE, g=0.0)
     g, ref = _render_both(orc, c0, cam, cfg, ocfg, cache=orc.OracleCache(cache, [0.0], 32))
-    err = rel_rmse(g, ref)
-    say("  rel-RMSE", err, "max|d|/max", np.abs(g - ref).max() / ref.max(), "mean", ref.mean())
     assert ref.max() > 0 and np.count_nonzero(ref) > 1000
-    assert err <= 1e-4
-    assert np.abs(g - ref).max() <= 1e-3 * ref.max()
+    # FP32 march against FP64: measured 7.4e-7 / 1.0e-6
+    check_err(g, ref, 1e-5, 1e-5, "c0 frame")
 
 
 def test_ragged_image_direct_only(orc, c0):
@@ -54,7 +53,7 @@ def test_ragged_image_direct_only(orc, c0):
     say("ragged 37x29 direct only, g=0.6")
     cam = sg.make_camera(c0["w"].seed, 1, 37, 29)
     g, ref = _render_both(orc, c0, cam, RenderConfig(g=0.6), orc.render_params(g=0.6))
-    assert rel_rmse(g, ref) <= 1e-4
+    check_err(g, ref, 2e-5, 1e-5, "ragged")  # measured 1.6e-6 / 7.1e-7
 
 
 def test_light_volume_three_lights_and_mask(orc):
@@ -72,10 +71,9 @@ def test_light_volume_three_lights_and_mask(orc):
         ctx.sync()
         ref = orc.render_pixels(os_, cam, orc.render_params(direct=orc.DIR_LIGHTVOL, g=-0.3,
                                                             light_mask=mask))
-        err = rel_rmse(img.cpu().numpy().reshape(-1, 3), ref)
-        say("  mask", mask, "rel-RMSE", err)
-        # transmittances are stored as binary16 (relative spacing 2^-11)
-        assert err <= 2e-3
+        # transmittances are stored as binary16 (relative spacing 2^-11 = 4.9e-4); measured
+        # 6.5e-5 / 1.05e-4, the bar is about two binary16 ulps per pixel
+        check_err(img.cpu().numpy().reshape(-1, 3), ref, 6e-4, 1e-3, f"mask {mask}")
 
 
 def test_spp_jitter_termination_cap_and_bins(orc, c0):
@@ -90,11 +88,9 @@ def test_spp_jitter_termination_cap_and_bins(orc, c0):
     ocfg = orc.render_params(spp=4, t_min=1e-3, max_steps=150, indirect=orc.IND_CACHE, g=0.25,
                              field_stride=3, seed=99)
     g, ref = _render_both(orc, c0, cam, cfg, ocfg, cache=orc.OracleCache(cache, [-0.5, 0.5], 16))
-    err = rel_rmse(g, ref)
-    say("  rel-RMSE", err)
-    # early termination compares T with t_min in FP32 vs FP64: a flipped decision changes a
-    # pixel by at most t_min times its remaining contribution
-    assert err <= 1e-3
+    # measured 7.0e-7 / 8.5e-7 (no early-termination decision flips between FP32 and FP64 on
+    # this view; a flip would move a pixel by at most t_min times its remaining contribution)
+    check_err(g, ref, 1e-5, 1e-5, "spp")
 
 
 def test_degenerate_views(orc, c0):
@@ -111,7 +107,7 @@ def test_degenerate_views(orc, c0):
     # a 1x1 image through the cube centre
     cam = sg.Camera((0.5, 0.5, -1.7), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), 10.0, 1, 1)
     g, ref = _render_both(orc, c0, cam, RenderConfig(g=0.1), orc.render_params(g=0.1))
-    assert rel_rmse(g, ref) <= 1e-4
+    check_err(g, ref, 1e-5, 1e-5, "1x1")  # measured 2.2e-7
 
 
 def test_invalid_arguments_are_rejected(c0):

@@ -4,15 +4,18 @@ limit against the ray marcher, and the FP64 image error reductions."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import (check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays,
+                        volume_as)
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def pts(orc):
+@pytest.fixture(scope="module", params=["f32", "f16"])
+def pts(orc, request):
+    """The C0 volume as FP32 and as binary16 (the path tracer's f16 instantiation)."""
     w, vol, tf, lights = scene_arrays("c0")
+    vol = volume_as(vol, request.param)
     ctx = gpu_context(vol, tf, lights)
     return dict(w=w, ctx=ctx, os=oracle_scene(orc, vol, tf, lights))
 
@@ -25,9 +28,8 @@ def test_path_tracer_matches_oracle(orc, pts, g, rr):
     img = pts["ctx"].render_path_traced(cam, spp, max_bounces=8, g=g, rr_start=rr, seed=13)
     pts["ctx"].sync()
     ref = orc.pt_pixels(pts["os"], cam, spp, max_bounces=8, g=g, rr_start=rr, seed=13)
-    err = rel_rmse(img.cpu().numpy().reshape(-1, 3), ref)
-    say("  rel-RMSE vs oracle (same random streams)", err)
-    assert err < 2e-2
+    # every path takes the oracle's decisions on these seeds: measured <= 1.1e-6 / 8.6e-7
+    check_err(img.cpu().numpy().reshape(-1, 3), ref, 1e-5, 1e-5, "same random streams")
     # an independent seed differs by the Monte Carlo error, far more than the pair above
     ref2 = orc.pt_pixels(pts["os"], cam, spp, max_bounces=8, g=g, rr_start=rr, seed=14)
     say("  rel-RMSE between two oracle seeds", rel_rmse(ref2, ref))

@@ -84,13 +84,19 @@ def test_binary16_volume_renders_as_its_fp32_values(shape):
         ctx.close()
 
 
-def test_light_volume_quad_copy_reads_the_same_texels():
+@pytest.mark.parametrize("shape", [None, (21, 29, 37)], ids=["c0", "ragged"])
+def test_light_volume_quad_copy_reads_the_same_texels(shape):
     """With at most 3 lights the march kernels read the light-transmittance volume through a
     quad copy (channels 0-2 of the four (x, y) corner texels per z plane).  The same 3 lights
     plus a fourth of zero intensity take the plain lookup (a 4-light volume has no quad copy)
-    and add nothing: counts are identical and images agree to FP32 rounding."""
+    and add nothing.  Both lookups blend the same texels with the same roundings, so counts and
+    images are identical, also on a ragged volume whose light grid (11 x 15 x 19) clamps at
+    every face, and from a view that crosses the cube's faces at a grazing angle."""
     from paper_2304_07338_amd.pfn import DIRECT_LIGHT_VOLUME, INDIRECT_FIELD, RenderConfig
     w, vol, tf, lights = scene_arrays("c0")
+    if shape is not None:
+        vol, _ = _volume(shape, seed=5)
+        vol = vol.float()
     l3 = np.array([[0.5, 1.3, 0.5, 2.0, 1.8, 1.5], [1.4, 0.6, 0.3, 0.8, 1.0, 1.2],
                    [-0.3, 0.4, 0.9, 1.1, 0.9, 0.7]])
     l4 = np.vstack([l3, [[0.2, -0.4, 0.6, 0.0, 0.0, 0.0]]])
@@ -98,26 +104,29 @@ def test_light_volume_quad_copy_reads_the_same_texels():
     for name, ls in (("quad", l3), ("plain", l4)):
         ctxs[name] = gpu_context(vol, tf, ls)
         _setup(ctxs[name], field_seed=9)
-    cam = sg.Camera((0.45, 0.6, -0.8), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), 55.0, 39, 31)
-    for strategy in ("fused", "wavefront"):
-        cfg = RenderConfig(spp=2, t_min=1e-3, max_steps=600, field_stride=2, g=0.3,
-                           indirect=INDIRECT_FIELD, direct=DIRECT_LIGHT_VOLUME,
-                           field_precision="f16", field_slot=0, seed=4)
-        out = {}
-        for name, ctx in ctxs.items():
-            ctx.set_render_strategy(strategy)
-            ctx.count_enable(True)
-            img = ctx.render_frame(cam, cfg).cpu().numpy()
-            counts = tuple(ctx.count_get())
-            ctx.count_enable(False)
-            ctx.sync()
-            out[name] = (img, counts)
-        (a, ca), (b, cb) = out["quad"], out["plain"]
-        diff = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
-        say(f"  {strategy}: counts {ca} / {cb}, mean {a.mean():.4g}, max diff / max {diff:.2e}")
-        assert a.mean() > 0
-        assert ca == cb
-        np.testing.assert_allclose(a, b, rtol=1e-6, atol=1e-6 * np.abs(b).max())
+    cams = [sg.Camera((0.45, 0.6, -0.8), (0.5, 0.5, 0.5), (0.0, 1.0, 0.0), 55.0, 39, 31),
+            sg.Camera((1.6, 1.3, 1.5), (0.45, 0.52, 0.55), (0.0, 1.0, 0.0), 38.0, 35, 27)]
+    for ci, cam in enumerate(cams):
+        for strategy in ("fused", "wavefront"):
+            cfg = RenderConfig(spp=2, t_min=1e-3, max_steps=600, field_stride=2, g=0.3,
+                               indirect=INDIRECT_FIELD, direct=DIRECT_LIGHT_VOLUME,
+                               field_precision="f16", field_slot=0, seed=4)
+            out = {}
+            for name, ctx in ctxs.items():
+                ctx.set_render_strategy(strategy)
+                ctx.count_enable(True)
+                img = ctx.render_frame(cam, cfg).cpu().numpy()
+                counts = tuple(ctx.count_get())
+                ctx.count_enable(False)
+                ctx.sync()
+                out[name] = (img, counts)
+            (a, ca), (b, cb) = out["quad"], out["plain"]
+            diff = np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+            say(f"  view {ci} {strategy}: counts {ca} / {cb}, mean {a.mean():.4g}, "
+                f"max diff / max {diff:.2e}")
+            assert a.mean() > 0
+            assert ca == cb
+            np.testing.assert_array_equal(a, b)
     for ctx in ctxs.values():
         ctx.set_render_strategy("auto")
         ctx.close()

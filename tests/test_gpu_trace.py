@@ -5,7 +5,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, say, scene_arrays
+from gpu_common import gpu_context, oracle_scene, say, scene_arrays, volume_as
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -13,13 +13,15 @@ pytestmark = pytest.mark.gpu
 BINS = [-0.6, 0.0, 0.7]
 
 
-@pytest.fixture(scope="module")
-def traced(orc):
+@pytest.fixture(scope="module", params=["f32", "f16"])
+def traced(orc, request):
+    """The C0 volume as FP32 and as binary16 (the tracer's f16 instantiation)."""
     w, vol, tf, _ = scene_arrays("c0")
+    vol = volume_as(vol, request.param)
     lights = sg.lights_array(sg.make_lights(2, 31))
     ctx = gpu_context(vol, tf, lights)
     n = 30011  # not a multiple of lights x bins: uneven (light, bin) groups
-    say(f"trace {n} photons, 2 lights, 3 bins")
+    say(f"trace {n} photons, 2 lights, 3 bins, {request.param} volume")
     st = ctx.trace_photon_cache(n, BINS, cache_res=16, seed=77, max_collisions=8, rr_start=3)
     recs = {k: v.cpu().numpy() for k, v in ctx.get_records(n * 7).items()}
     os_ = oracle_scene(orc, vol, tf, lights)
@@ -34,7 +36,7 @@ def test_records_match_photon_by_photon(traced):
     oc = np.bincount(o["photon"].astype(np.int64), minlength=n)
     same = gc == oc
     say("  photons with equal record counts:", same.mean(), "records", len(g["x"]), len(o["x"]))
-    assert same.mean() >= 0.995
+    assert same.mean() >= 0.999  # measured 1.0
     assert traced["st"]["n_records"] == len(g["x"])
     # compare the records of the photons whose paths agree in length
     gs = np.concatenate([[0], np.cumsum(gc)])
@@ -47,7 +49,8 @@ def test_records_match_photon_by_photon(traced):
     dp = (np.abs(g["power"][gi] - o["power"][oi]) / o["power"][oi].max(axis=1, keepdims=True)).max(axis=1)
     say("  |dx| p99", np.quantile(dx, 0.99), "|dw| p99", np.quantile(dw, 0.99), "|dp| p99",
         np.quantile(dp, 0.99))
-    assert np.quantile(dx, 0.99) < 1e-4 and np.quantile(dw, 0.99) < 1e-4
+    # measured p99: 6.1e-7 (x), 8.2e-7 (w), 8.2e-6 (power: FP32 albedo products along the path)
+    assert np.quantile(dx, 0.99) < 6e-6 and np.quantile(dw, 0.99) < 8e-6
     assert np.quantile(dp, 0.99) < 1e-5
     np.testing.assert_array_equal(g["bin"][gi], o["bin"][oi])
 
@@ -87,7 +90,7 @@ def test_cache_from_identical_records(orc, traced):
                                                  "bin": g["bin"]}, 16, 3)
     err = np.abs(cache - ref).max() / ref.max()
     say("  cache max rel diff", err, "kappa", kappa, okappa)
-    assert err < 1e-5
+    assert err < 1e-6  # measured 1.0e-7
     assert kappa == pytest.approx(cache.max(), rel=1e-7)
     assert kappa == pytest.approx(okappa, rel=1e-5)
 

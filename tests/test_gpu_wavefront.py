@@ -2,7 +2,8 @@
 matrix-core field tiles) against the fused kernel and the FP64 oracle.
 
 Both forms run the same per-ray arithmetic; they differ in the order in which the FP32 terms
-W * L_i are added to a pixel, so they agree to FP32 rounding (bar: relative RMSE 1e-5) and give
+W * L_i are added to a pixel, so they agree to FP32 rounding (measured at most 6.1e-7 relative
+RMSE and 5.7e-7 of the image maximum per value; bars 6e-6 for both) and give
 identical march-step and query counts.  Cases cover many rounds per ray (stride 1, where a ray
 stores up to 32 queries per round), frames of more ray samples than one round holds (2^21),
 ragged tiles, several samples per pixel, every matrix-core precision, both direct-light modes,
@@ -10,7 +11,7 @@ and a batch of jobs that must render exactly as its jobs do alone."""
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
@@ -72,11 +73,10 @@ def test_wavefront_matches_fused(wctx, case):
                max_steps=1 << 20 if stride == 1 else 400, t_min=0.0 if stride == 1 else 1e-3)
     r = _both(wctx["ctx"], cam, cfg)
     (a, ca), (b, cb) = r["fused"], r["wavefront"]
-    err = rel_rmse(b, a)
-    say(f"  {tag}: wavefront vs fused rel-RMSE {err:.2e}, counts {ca} / {cb}, mean {a.mean():.4g}")
+    say(f"  {tag}: counts {ca} / {cb}, mean {a.mean():.4g}")
     assert a.mean() > 0
     assert tuple(ca) == tuple(cb)
-    assert err <= 1e-5
+    check_err(b, a, 6e-6, 6e-6, f"{tag}: wavefront vs fused")
 
 
 def test_wavefront_matches_oracle(orc, wctx):
@@ -95,9 +95,8 @@ def test_wavefront_matches_oracle(orc, wctx):
     op = orc.render_params(spp=2, t_min=1e-3, max_steps=400, field_stride=3, g=0.35,
                            indirect=orc.IND_FIELD, direct=orc.DIR_LIGHTVOL, seed=9)
     ref = orc.render_pixels(os_, cam, op, field=(desc, p, 0, 1e-2))
-    err = rel_rmse(img.cpu().numpy().reshape(-1, 3), ref)
-    say(f"  wavefront f32 vs oracle rel-RMSE {err:.2e}")
-    assert err <= 2e-3  # the light-transmittance volume is stored in binary16
+    # the light-transmittance volume is stored in binary16; measured 8.9e-5 / 8.3e-5
+    check_err(img.cpu().numpy().reshape(-1, 3), ref, 6e-4, 1e-3, "wavefront f32 vs oracle")
 
 
 @pytest.mark.parametrize("levels", [12, 8, 6])
@@ -118,11 +117,9 @@ def test_wavefront_level_counts(wctx, levels):
     cam = sg.make_camera(wctx["w"].seed, 25, 48, 36)
     r = _both(ctx, cam, _cfg(spp=2, field_slot=2))
     (a, ca), (b, cb) = r["fused"], r["wavefront"]
-    err = rel_rmse(b, a)
-    say(f"  {levels} levels: wavefront vs fused rel-RMSE {err:.2e}, mean {a.mean():.4g}")
     assert a.mean() > 0
     assert tuple(ca) == tuple(cb)
-    assert err <= 1e-5
+    check_err(b, a, 6e-6, 6e-6, f"{levels} levels: wavefront vs fused")
 
 
 def test_wavefront_frame_larger_than_one_round(wctx):
@@ -132,10 +129,8 @@ def test_wavefront_frame_larger_than_one_round(wctx):
     cfg = _cfg(spp=2, field_stride=4)
     r = _both(wctx["ctx"], cam, cfg)
     (a, ca), (b, cb) = r["fused"], r["wavefront"]
-    err = rel_rmse(b, a)
-    say(f"  1280x960x2: wavefront vs fused rel-RMSE {err:.2e}, counts {ca} / {cb}")
     assert tuple(ca) == tuple(cb)
-    assert err <= 1e-5
+    check_err(b, a, 6e-6, 6e-6, "1280x960x2: wavefront vs fused")
 
 
 def test_wavefront_batch_equals_single_renders(wctx):
