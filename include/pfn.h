@@ -35,7 +35,7 @@ typedef enum {
   PFN_ERR_OUT_OF_MEMORY = -2,
   PFN_ERR_HIP = -3,
   PFN_ERR_NOT_READY = -4,   /* a prerequisite (volume, cache, field, ...) is missing */
-  PFN_ERR_UNSUPPORTED = -5,
+  PFN_ERR_UNSUPPORTED = -5, /* e.g. uniform g with photon-map targets */
   PFN_ERR_NUMERIC = -6      /* NaN or Inf met (e.g. in the training loss) */
 } pfn_status;
 
@@ -207,10 +207,14 @@ typedef struct {
   float radius;         /* photon-map targets: the final (maximum) query radius, cube units */
   int staggered;        /* photon-map targets: 1 = the staggered schedule of Section 3.5.2 */
   int loss;             /* 0: L2 (the configuration); 1: relative L2 (Section 3.5.1) */
+  int g_sampling;       /* 0: g drawn from the phase pool (Section 3.5.1); 1: g uniform over
+                           [g_0, g_last], target = the cache gather interpolated linearly in g
+                           between the two neighbouring bins (cache targets, >= 2 bins) */
 } pfn_train_params;
 
 /* Section 3.5: each step draws a fresh batch (uniform x, uniform direction, g from the cache
- * bins), takes its targets, runs forward, L2 loss, backward and Adam.  Targets are Eq. (6) of
+ * bins, or with g_sampling = 1 uniform between the first and last bin), takes its targets, runs
+ * forward, L2 loss, backward and Adam.  Targets are Eq. (6) of
  * value / kappa (kappa: the cache maximum), the value being
  *   target 0: the cache gather at x in the sample's bin;
  *   target 1: the photon-map estimate of Eq. (5) at (x, direction) in the sample's bin, with
@@ -233,10 +237,12 @@ pfn_status pfn_train_step_radius(const pfn_train_params *params, int step, float
  * Host only, no context, no GPU.  Returns PFN_ERR_INVALID_ARG for NULL pointers, steps < 1,
  * step outside [0, steps), decay_interval < 1 or decay_start < 0. */
 pfn_status pfn_train_lr_at(const pfn_train_params *params, int step, float *host_lr);
-/* The training-batch generator alone (for checking): step `step`'s n samples. */
+/* The training-batch generator alone (for checking): step `step`'s n samples, g_sampling as in
+ * pfn_train_params (with one bin, 1 acts as 0).  dev_bin receives the sample's bin (uniform g:
+ * the lower of the two neighbouring bins).  PFN_ERR_NOT_READY without a cache. */
 pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
-                           float *dev_xyz, float *dev_dir, float *dev_g, int32_t *dev_bin,
-                           float *dev_target);
+                           int g_sampling, float *dev_xyz, float *dev_dir, float *dev_g,
+                           int32_t *dev_bin, float *dev_target);
 /* One Adam step (bias-corrected, step t >= 1) on the selected field with gradient dev_grad. */
 pfn_status pfn_field_adam_step(pfn_context *ctx, const float *dev_grad, int64_t t, float lr,
                                float beta1, float beta2, float eps);

@@ -116,6 +116,11 @@ void orc_adam_step(int64_t n, double *param, const double *grad, double *m, doub
 double orc_lr_at(int64_t step, double lr0, double decay, int64_t start_step, int64_t interval);
 void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache, double kappa,
                      double psi, double *xyz, double *dir, double *g, int *bin, double *target);
+/* g_mode 0: g from the phase pool (the paper's batches); 1: g uniform over [g_0, g_last] with the
+ * target interpolated linearly in g between the neighbouring bins. */
+void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache,
+                          double kappa, double psi, int g_mode, double *xyz, double *dir,
+                          double *g, int *bin, double *target);
 
 /* ---------------- Photon tracing (Algorithm 1) ---------------- */
 typedef struct {

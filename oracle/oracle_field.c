@@ -364,16 +364,22 @@ double orc_lr_at(int64_t step, double lr0, double decay, int64_t start_step, int
 }
 
 /* ------------------------------------------------------------------ training batches */
-void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache, double kappa,
-                     double psi, double *xyz, double *dir, double *g, int *bin, double *target) {
+/* A batch of Section 3.5.1: uniform positions and directions, and for each sample a phase value
+ * and its target, Eq. (6) of the cache value over kappa.  g_mode 0 takes g from the phase pool
+ * (a uniformly drawn bin, the target that bin's gather); g_mode 1 turns the same uniform draw
+ * into g uniform over [g_0, g_last] and takes as target the gather interpolated linearly in g
+ * between the two neighbouring bins (the same interpolation as the renderer's cache gather),
+ * reporting the lower bin. */
+void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache,
+                          double kappa, double psi, int g_mode, double *xyz, double *dir,
+                          double *g, int *bin, double *target) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     orc_rng r;
     orc_rng_init(&r, seed, ((uint64_t)step << 32) | (uint64_t)(uint32_t)i, ORC_STREAM_TRAIN);
     double x[3];
     for (int a = 0; a < 3; ++a) x[a] = orc_rng_next(&r);
-    int b = (int)floor(orc_rng_next(&r) * cache->n_bins);
-    if (b > cache->n_bins - 1) b = cache->n_bins - 1;
+    const double u = orc_rng_next(&r);
     double u1 = orc_rng_next(&r), u2 = orc_rng_next(&r);
     double w[3];
     orc_iso_dir(u1, u2, w);
@@ -381,12 +387,29 @@ void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *ca
       xyz[3 * i + a] = x[a];
       dir[3 * i + a] = w[a];
     }
-    g[i] = cache->g_bins[b];
-    if (bin) bin[i] = b;
     double v[3];
-    orc_cache_gather_bin(cache, b, x, v);
+    int b;
+    if (g_mode == 1 && cache->n_bins > 1) {
+      const double g0 = cache->g_bins[0], g1 = cache->g_bins[cache->n_bins - 1];
+      const double gg = g0 + u * (g1 - g0);
+      b = 0;
+      while (b + 2 < cache->n_bins && gg >= cache->g_bins[b + 1]) ++b;
+      g[i] = gg;
+      orc_cache_gather(cache, x, gg, v);
+    } else {
+      b = (int)floor(u * cache->n_bins);
+      if (b > cache->n_bins - 1) b = cache->n_bins - 1;
+      g[i] = cache->g_bins[b];
+      orc_cache_gather_bin(cache, b, x, v);
+    }
+    if (bin) bin[i] = b;
     for (int c = 0; c < 3; ++c) target[3 * i + c] = orc_log_encode(v[c] / kappa, psi);
   }
+}
+
+void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache, double kappa,
+                     double psi, double *xyz, double *dir, double *g, int *bin, double *target) {
+  orc_train_batch_mode(seed, step, n, cache, kappa, psi, 0, xyz, dir, g, bin, target);
 }
 
 double orc_field_loss_grad(const orc_field_desc *d, const double *params, int rounding, int64_t n,

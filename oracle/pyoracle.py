@@ -146,6 +146,8 @@ def lib():
         L.orc_lr_at.argtypes = [C.c_int64, C.c_double, C.c_double, C.c_int64, C.c_int64]
         L.orc_train_batch.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.POINTER(Cache),
                                       C.c_double, C.c_double, dp, dp, dp, ip, dp]
+        L.orc_train_batch_mode.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.POINTER(Cache),
+                                           C.c_double, C.c_double, C.c_int, dp, dp, dp, ip, dp]
         L.orc_trace.argtypes = [C.POINTER(Scene), C.POINTER(TraceParams), C.c_uint64, C.c_uint64,
                                 C.POINTER(TraceStats), C.c_uint64, dp, dp, dp, ip, u64p, u64p]
         L.orc_splat_cache.restype = C.c_double
@@ -357,14 +359,17 @@ def lr_at(step, lr0=9e-4, decay=0.92, start_step=1400, interval=25) -> float:
     return lib().orc_lr_at(step, lr0, decay, start_step, interval)
 
 
-def train_batch(seed, step, n, cache: OracleCache, kappa, psi=5.0):
+def train_batch(seed, step, n, cache: OracleCache, kappa, psi=5.0, g_sampling="pool"):
+    """g_sampling "pool": g from the cache's bins; "uniform": g uniform over [g_0, g_last] with
+    targets interpolated linearly in g between the neighbouring bins."""
     xyz = np.zeros((n, 3))
     dirs = np.zeros((n, 3))
     g = np.zeros(n)
     b = np.zeros(n, dtype=np.int32)
     tgt = np.zeros((n, 3))
-    lib().orc_train_batch(seed, step, n, cache.ref, kappa, psi, _ptr(xyz), _ptr(dirs), _ptr(g),
-                          _ptr(b, ip), _ptr(tgt))
+    mode = {"pool": 0, "uniform": 1}[g_sampling]
+    lib().orc_train_batch_mode(seed, step, n, cache.ref, kappa, psi, mode, _ptr(xyz), _ptr(dirs),
+                               _ptr(g), _ptr(b, ip), _ptr(tgt))
     return xyz, dirs, g, b, tgt
 
 

@@ -50,7 +50,7 @@ class TrainParams(C.Structure):
                 ("decay", C.c_float), ("decay_start", C.c_int), ("decay_interval", C.c_int),
                 ("precision", C.c_int), ("seed", C.c_uint64), ("target", C.c_int),
                 ("knn_k", C.c_int), ("radius", C.c_float), ("staggered", C.c_int),
-                ("loss", C.c_int)]
+                ("loss", C.c_int), ("g_sampling", C.c_int)]
 
 
 class CameraS(C.Structure):
@@ -97,7 +97,8 @@ SIGNATURES = {
     "pfn_field_forward_backward": (C.c_int, [ctxp, C.c_int, vp, vp, vp, vp, C.c_int64, C.c_int,
                                              C.POINTER(C.c_double), vp]),
     "pfn_train_field": (C.c_int, [ctxp, C.POINTER(TrainParams), C.POINTER(C.c_float)]),
-    "pfn_train_batch": (C.c_int, [ctxp, C.c_uint64, C.c_int64, C.c_int64, vp, vp, vp, vp, vp]),
+    "pfn_train_batch": (C.c_int, [ctxp, C.c_uint64, C.c_int64, C.c_int64, C.c_int, vp, vp, vp,
+                                  vp, vp]),
     "pfn_field_adam_step": (C.c_int, [ctxp, vp, C.c_int64, C.c_float, C.c_float, C.c_float,
                                       C.c_float]),
     "pfn_render_frame": (C.c_int, [ctxp, C.POINTER(CameraS), C.POINTER(RenderParams), vp]),

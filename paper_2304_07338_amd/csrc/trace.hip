@@ -296,6 +296,7 @@ static pfn_status trace_alloc(pfn_context *ctx, uint64_t slots, uint64_t photons
   ctx->rec_bin = nullptr;
   ctx->rec_cnt = nullptr;
   ctx->rec_cap = ctx->cnt_cap = 0;
+  ctx->rec_photons = ctx->rec_count = 0;  // the old records are gone, also if allocation fails
   PFN_HIP(ctx, hipMalloc((void **)&ctx->rec_x, slots * 12));
   PFN_HIP(ctx, hipMalloc((void **)&ctx->rec_w, slots * 12));
   PFN_HIP(ctx, hipMalloc((void **)&ctx->rec_p, slots * 12));

@@ -26,6 +26,8 @@ struct SampleSrc {
   int cache_res, n_bins;
   float g_bins[8];
   float inv_kappa, psi;
+  int g_uniform;  // 1: g uniform over [g_0, g_last], targets interpolated in g between bins
+  float g_span;   // g_last - g_0
 };
 
 __device__ __forceinline__ float log_target(float v, float psi) {
@@ -40,28 +42,46 @@ __device__ __forceinline__ void gen_sample(const SampleSrc &s, int64_t i, f3 &x,
   x.x = r.next();
   x.y = r.next();
   x.z = r.next();
-  // bin = floor(u * n_bins) with u = (k + 1/2) 2^-23, in exact integer arithmetic
+  // u = (k + 1/2) 2^-23 (exact in FP32).  Pool batches: bin = floor(u * n_bins), in exact
+  // integer arithmetic, and g its pool value.  Uniform-g batches: g = g_0 + u (g_last - g_0),
+  // bin the lower of the two neighbouring bins and wb the weight of the upper one.
   uint32_t k = r.next_u32() >> 9;
-  bin = (int)(((2ull * k + 1ull) * (uint64_t)s.n_bins) >> 24);
+  float wb = 0.0f;
+  if (s.g_uniform) {
+    const float u = (float)(2u * k + 1u) * 0x1p-24f;
+    g = fmaf(u, s.g_span, s.g_bins[0]);
+    bin = 0;
+    while (bin + 2 < s.n_bins && g >= s.g_bins[bin + 1]) ++bin;
+    wb = (g - s.g_bins[bin]) / (s.g_bins[bin + 1] - s.g_bins[bin]);
+  } else {
+    bin = (int)(((2ull * k + 1ull) * (uint64_t)s.n_bins) >> 24);
+    g = s.g_bins[bin];
+  }
   float u1 = r.next(), u2 = r.next();
   w = iso_dir(u1, u2);
-  g = s.g_bins[bin];
   const int R = s.cache_res;
   int i0, i1, j0, j1, k0, k1;
   float fx, fy, fz;
   tri_axis(x.x, R, i0, i1, fx);
   tri_axis(x.y, R, j0, j1, fy);
   tri_axis(x.z, R, k0, k1, fz);
-  const float4 *c = s.cache + (size_t)bin * R * R * R;
   float v0 = 0.f, v1 = 0.f, v2 = 0.f;
+  for (int bi = 0; bi < (s.g_uniform ? 2 : 1); ++bi) {
+    const float4 *c = s.cache + (size_t)(bin + bi) * R * R * R;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    int ix = (q & 1) ? i1 : i0, iy = (q & 2) ? j1 : j0, iz = (q & 4) ? k1 : k0;
-    float wq = ((q & 1) ? fx : 1.0f - fx) * ((q & 2) ? fy : 1.0f - fy) * ((q & 4) ? fz : 1.0f - fz);
-    float4 e = c[((size_t)iz * R + iy) * R + ix];
-    v0 = fmaf(wq, e.x, v0);
-    v1 = fmaf(wq, e.y, v1);
-    v2 = fmaf(wq, e.z, v2);
+    for (int q = 0; q < 8; ++q) {
+      int ix = (q & 1) ? i1 : i0, iy = (q & 2) ? j1 : j0, iz = (q & 4) ? k1 : k0;
+      float wq = ((q & 1) ? fx : 1.0f - fx) * ((q & 2) ? fy : 1.0f - fy) * ((q & 4) ? fz : 1.0f - fz);
+      float4 e = c[((size_t)iz * R + iy) * R + ix];
+      a0 = fmaf(wq, e.x, a0);
+      a1 = fmaf(wq, e.y, a1);
+      a2 = fmaf(wq, e.z, a2);
+    }
+    const float wbin = s.g_uniform ? (bi ? wb : 1.0f - wb) : 1.0f;
+    v0 = fmaf(wbin, a0, v0);
+    v1 = fmaf(wbin, a1, v1);
+    v2 = fmaf(wbin, a2, v2);
   }
   tgt[0] = log_target(v0 * s.inv_kappa, s.psi);
   tgt[1] = log_target(v1 * s.inv_kappa, s.psi);
@@ -238,54 +258,102 @@ struct ActT<P_F32> {
   typedef float type;
 };
 
-// Scatter the encoder-input gradients of this lane's 4 levels into the grid gradients.
-__device__ __forceinline__ void scatter_grid_grads(const TrainArgs &a, int q, f3 x, float u0,
-                                                   float u1, const float gp[8], const float gd[8]) {
+// ------------------------------------------------------------------ encoder-gradient scatter
+// The grid gradients take FP32 atomics, whose cost is set by the number of memory requests, not
+// of lanes: lanes of one instruction that hit one 64-byte segment share a request.  A lane
+// therefore does not scatter its own sample's corners (every lane a different segment); the wave
+// stages its 16 samples' encoder gradients in LDS and scatters them with a lane mapping in which
+// the 4 floats of an x-neighbour corner pair (2 features of corner x0, 2 of corner x1: one
+// 16-byte run on dense levels, and on hashed levels whenever x0 is even, since the hash's
+// x prime is 1) come from 4 consecutive lanes.
+#define TRAIN_WAVES (TRAIN_THREADS / 64)
+#define DZ_STRIDE 65  // floats per staged sample (64 gradients, padded against bank conflicts)
+
+struct StagedGrads {
+  float dz[TRAIN_WAVES][16][DZ_STRIDE];  // [wave][sample][2L position, then 2L direction]
+  float xu[TRAIN_WAVES][16][6];          // x, y, z, u0, u1, valid
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane (q, nl) holds the gradients of sample nl for levels 4q..4q+3: position gp[2j + f] and
+// direction gd[2j + f] of level 4q + j, feature f.
+__device__ __forceinline__ void stage_grid_grads(StagedGrads &S, int wv, int q, int nl, bool valid,
+                                                 f3 x, float u0, float u1, const float gp[8],
+                                                 const float gd[8]) {
+  float *d = S.dz[wv][nl];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    d[8 * q + r] = valid ? gp[r] : 0.0f;
+    d[32 + 8 * q + r] = valid ? gd[r] : 0.0f;
+  }
+  if (q == 0) {
+    float *c = S.xu[wv][nl];
+    c[0] = x.x;
+    c[1] = x.y;
+    c[2] = x.z;
+    c[3] = u0;
+    c[4] = u1;
+    c[5] = valid ? 1.0f : 0.0f;
+  }
+}
+
+__device__ __forceinline__ void scatter_staged(const TrainArgs &a, const StagedGrads &S, int wv,
+                                               int lane) {
   const FieldDev &F = a.F;
+  // position levels: 16 lanes per (level, sample), 4 (level, sample) pairs per instruction
+  {
+    const int r = lane & 15, cp = r >> 2, xb = (r >> 1) & 1, feat = r & 1;
+    const int smp4 = lane >> 4;
 #pragma unroll 1
-  for (int j = 0; j < 4; ++j) {
-    int lv = 4 * q + j;
-    if (lv >= F.levels) break;
-    {
-      int N = F.pos.res[lv];
-      uint32_t off = F.pos.off[lv];
-      bool dense = (F.pos.dense_mask >> lv) & 1u;
+    for (int it = 0; it < 4 * F.levels; ++it) {
+      const int lv = it >> 2, smp = 4 * (it & 3) + smp4;
+      const float *xu = S.xu[wv][smp];
+      const float gv = S.dz[wv][smp][2 * lv + feat];
+      if (xu[5] == 0.0f) continue;
+      const int N = F.pos.res[lv];
+      const uint32_t off = F.pos.off[lv];
+      const bool dense = (F.pos.dense_mask >> lv) & 1u;
       int cx, cy, cz;
       float fx, fy, fz;
-      level_cell(x.x, N, cx, fx);
-      level_cell(x.y, N, cy, fy);
-      level_cell(x.z, N, cz, fz);
-      uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1)),
-                 vz = (uint32_t)(cz + ((k >> 2) & 1));
-        uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
-        float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy) *
-                  (((k >> 2) & 1) ? fz : 1.0f - fz);
-        float *e = a.grad_pos + 2 * (size_t)(off + idx);
-        atomicAdd(e, w * gp[2 * j]);
-        atomicAdd(e + 1, w * gp[2 * j + 1]);
-      }
+      level_cell(xu[0], N, cx, fx);
+      level_cell(xu[1], N, cy, fy);
+      level_cell(xu[2], N, cz, fz);
+      const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + (cp & 1)),
+                     vz = (uint32_t)(cz + (cp >> 1));
+      const uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+      const uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+      const float w = (xb ? fx : 1.0f - fx) * ((cp & 1) ? fy : 1.0f - fy) *
+                      ((cp >> 1) ? fz : 1.0f - fz);
+      atomicAdd(a.grad_pos + 2 * (size_t)(off + idx) + feat, w * gv);
     }
-    {
-      int N = F.dir.res[lv];
-      uint32_t off = F.dir.off[lv];
-      bool dense = (F.dir.dense_mask >> lv) & 1u;
+  }
+  // direction levels: 8 lanes per (level, sample), 8 pairs per instruction
+  {
+    const int r = lane & 7, cp = r >> 2, xb = (r >> 1) & 1, feat = r & 1;
+    const int smp8 = lane >> 3;
+#pragma unroll 1
+    for (int it = 0; it < 2 * F.levels; ++it) {
+      const int lv = it >> 1, smp = 8 * (it & 1) + smp8;
+      const float *xu = S.xu[wv][smp];
+      const float gv = S.dz[wv][smp][32 + 2 * lv + feat];
+      if (xu[5] == 0.0f) continue;
+      const int N = F.dir.res[lv];
+      const uint32_t off = F.dir.off[lv];
+      const bool dense = (F.dir.dense_mask >> lv) & 1u;
       int cx, cy;
       float fx, fy;
-      level_cell(u0, N, cx, fx);
-      level_cell(u1, N, cy, fy);
-      uint32_t s1 = (uint32_t)(N + 1);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1));
-        uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
-        float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy);
-        float *e = a.grad_dir + 2 * (size_t)(off + idx);
-        atomicAdd(e, w * gd[2 * j]);
-        atomicAdd(e + 1, w * gd[2 * j + 1]);
-      }
+      level_cell(xu[3], N, cx, fx);
+      level_cell(xu[4], N, cy, fy);
+      const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + cp);
+      const uint32_t s1 = (uint32_t)(N + 1);
+      const uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+      const float w = (xb ? fx : 1.0f - fx) * (cp ? fy : 1.0f - fy);
+      atomicAdd(a.grad_dir + 2 * (size_t)(off + idx) + feat, w * gv);
     }
   }
 }
@@ -296,10 +364,12 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
   // One 16-sample tile per wave and no loop over tiles: the weight operands are then not
   // loop-invariant, so the compiler streams them from cache instead of pinning them in registers.
   const int lane = lane_id(), q = lane >> 4, nl = lane & 15;
-  const int64_t tile = (int64_t)blockIdx.x * (TRAIN_THREADS / 64) + (threadIdx.x >> 6);
+  const int wv = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * TRAIN_WAVES + wv;
   const int64_t ntiles = a.ldn / 16;
   const int L = a.F.levels;
   T *act = reinterpret_cast<T *>(a.act);
+  __shared__ StagedGrads S;
   double wave_loss = 0.0;
   if (tile < ntiles) {
     const int64_t i = tile * 16 + nl;
@@ -434,7 +504,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[mt] = nxt[mt];
       }
-      if (valid) {
+      {
         float gp[8], gd[8];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -443,7 +513,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
           gd[r] = acc[2][r];
           gd[4 + r] = acc[3][r];
         }
-        scatter_grid_grads(a, q, x, u0, u1, gp, gd);
+        stage_grid_grads(S, wv, q, nl, valid, x, u0, u1, gp, gd);
       }
     } else {
       typedef Mma<P> M;
@@ -544,7 +614,7 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
           acc[mt] = c;
         }
       }
-      if (valid) {
+      {
         float gp[8], gd[8];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -553,9 +623,11 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
           gd[r] = acc[2][r];
           gd[4 + r] = acc[3][r];
         }
-        scatter_grid_grads(a, q, x, u0, u1, gp, gd);
+        stage_grid_grads(S, wv, q, nl, valid, x, u0, u1, gp, gd);
       }
     }
+    wave_sync_lds();
+    scatter_staged(a, S, wv, lane);
     if (q == 0) wave_loss += (double)lsum[0] + (double)lsum[1] + (double)lsum[2];
   }
   for (int off = 32; off > 0; off >>= 1) wave_loss += __shfl_down(wave_loss, off);
@@ -824,7 +896,8 @@ static pfn_status check_training_field(pfn_context *ctx, FieldSlot &f) {
 
 static int prec_from(pfn_dtype d) { return d == PFN_F32 ? P_F32 : d == PFN_BF16 ? P_BF16 : P_F16; }
 
-static SampleSrc make_src(pfn_context *ctx, uint64_t seed, int64_t step, float psi) {
+static SampleSrc make_src(pfn_context *ctx, uint64_t seed, int64_t step, float psi,
+                          int g_sampling) {
   SampleSrc s{};
   s.seed = seed;
   s.step = step;
@@ -834,12 +907,17 @@ static SampleSrc make_src(pfn_context *ctx, uint64_t seed, int64_t step, float p
   for (int b = 0; b < ctx->cache_bins; ++b) s.g_bins[b] = ctx->g_bins[b];
   s.inv_kappa = (float)(1.0 / ctx->kappa);
   s.psi = psi;
+  s.g_uniform = (g_sampling == 1 && ctx->cache_bins > 1) ? 1 : 0;
+  s.g_span = (float)((double)ctx->g_bins[ctx->cache_bins - 1] - (double)ctx->g_bins[0]);
   return s;
 }
 
 extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
-                                      float *xyz, float *dir, float *g, int32_t *bin, float *tgt) {
+                                      int g_sampling, float *xyz, float *dir, float *g,
+                                      int32_t *bin, float *tgt) {
   if (!ctx) return PFN_ERR_INVALID_ARG;
+  if (g_sampling != 0 && g_sampling != 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "g_sampling: 0 (pool) or 1 (uniform)");
   if (n < 0 || n > ((int64_t)1 << 32)) return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "n in [0, 2^32]");
   if (step < 0 || step >= ((int64_t)1 << 31))
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "step in [0, 2^31)");
@@ -847,7 +925,7 @@ extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t s
   if (n == 0) return PFN_OK;
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   float psi = ctx->fields[ctx->cur_field].init ? ctx->fields[ctx->cur_field].desc.psi : 5.0f;
-  SampleSrc s = make_src(ctx, seed, step, psi);
+  SampleSrc s = make_src(ctx, seed, step, psi, g_sampling);
   hipLaunchKernelGGL(train_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
                      ctx->stream, s, n, xyz, dir, g, bin, tgt);
   PFN_HIP(ctx, hipGetLastError());
@@ -971,6 +1049,12 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "target: 0 (cache) or 1 (photon map)");
   if (p->loss != 0 && p->loss != 1)
     return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "loss: 0 (L2) or 1 (relative L2)");
+  if (p->g_sampling != 0 && p->g_sampling != 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "g_sampling: 0 (pool) or 1 (uniform)");
+  if (p->g_sampling == 1 && ctx->cache_bins < 2)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "uniform g needs at least two cache bins");
+  if (p->g_sampling == 1 && p->target != 0)
+    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "uniform g is supported for cache targets only");
   const bool map_targets = p->target == 1;
   if (map_targets) {
     if (!(std::isfinite(p->radius) && p->radius > 0.0f && p->radius <= 2.0f))
@@ -1011,7 +1095,7 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
   for (int s = 0; s < p->steps; ++s) {
     st = refresh_train_images(ctx, f, prec);
     if (st) return st;
-    SampleSrc src = make_src(ctx, p->seed, s, f.desc.psi);
+    SampleSrc src = make_src(ctx, p->seed, s, f.desc.psi, p->g_sampling);
     if (map_targets) {
       // the step's batch (the same samples as the cache targets would use), its Eq. (5)
       // estimates and their Eq. (6) encoding

@@ -65,6 +65,7 @@ class RenderConfig:
 
 
 LOSSES = {"l2": 0, "rel": 1}
+G_SAMPLING = {"pool": 0, "uniform": 1}
 
 
 @dataclasses.dataclass
@@ -85,13 +86,15 @@ class TrainConfig:
     radius: float = 0.05
     staggered: bool = False
     loss: str = "l2"        # or "rel" (relative L2 of Section 3.5.1)
+    g_sampling: str = "pool"  # or "uniform": g uniform between the first and last bin
 
     def struct(self) -> _ffi.TrainParams:
         return _ffi.TrainParams(self.steps, self.log2_batch, self.lr, self.beta1, self.beta2,
                                 self.eps, self.decay, self.decay_start, self.decay_interval,
                                 DTYPES[self.precision], self.seed,
                                 {"cache": 0, "photon_map": 1}[self.target], self.knn_k,
-                                self.radius, int(self.staggered), LOSSES[self.loss])
+                                self.radius, int(self.staggered), LOSSES[self.loss],
+                                G_SAMPLING[self.g_sampling])
 
 
 def train_step_radius(cfg: "TrainConfig", step: int) -> float:
@@ -364,7 +367,7 @@ class Context:
         self._ok(self.lib.pfn_train_field(self.h, C.byref(p), ptr))
         return hist
 
-    def train_batch(self, seed: int, step: int, n: int):
+    def train_batch(self, seed: int, step: int, n: int, g_sampling: str = "pool"):
         import torch
         dev = f"cuda:{self.device}"
         xyz = torch.empty((n, 3), dtype=torch.float32, device=dev)
@@ -372,8 +375,8 @@ class Context:
         g = torch.empty(n, dtype=torch.float32, device=dev)
         b = torch.empty(n, dtype=torch.int32, device=dev)
         tgt = torch.empty((n, 3), dtype=torch.float32, device=dev)
-        self._ok(self.lib.pfn_train_batch(self.h, seed, step, n, _ptr(xyz), _ptr(dirs), _ptr(g),
-                                          _ptr(b), _ptr(tgt)))
+        self._ok(self.lib.pfn_train_batch(self.h, seed, step, n, G_SAMPLING[g_sampling], _ptr(xyz),
+                                          _ptr(dirs), _ptr(g), _ptr(b), _ptr(tgt)))
         return xyz, dirs, g, b, tgt
 
     def field_adam_step(self, grad, t: int, lr: float, beta1=0.9, beta2=0.99, eps=1e-15):

@@ -6,7 +6,8 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import gpu_context, say, scene_arrays, smooth_cache
+from gpu_common import (coord_jitter, coord_moves, gpu_context, say, scene_arrays,
+                        smooth_cache)
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +44,7 @@ def test_training_batch_matches_oracle(orc, tctx):
     assert np.abs(dirs - od).max() < 2e-6
     d = np.abs(tgt - ot)
     say("  target max |d|", d.max())
-    assert d.max() < 2e-5
+    assert d.max() < 3e-7  # measured 3.0e-8
 
 
 def _random_params(orc, desc, seed):
@@ -58,52 +59,142 @@ def _random_params(orc, desc, seed):
     return p, L
 
 
-def _segments(L):
-    segs = {"pos_grid": (0, L.pos_params), "dir_grid": (L.pos_params, L.mlp_off)}
+def test_uniform_g_batch_matches_oracle(orc, tctx):
+    """Batches with g uniform over [g_0, g_last]: positions and directions as in pool batches,
+    g from the same draw (FP32 fma against FP64: within a few ulps), the lower bin, and targets
+    from the gather interpolated linearly in g."""
+    ctx, cache = tctx
+    n = 5000
+    xyz, dirs, g, b, tgt = (t.cpu().numpy() for t in ctx.train_batch(42, 17, n, "uniform"))
+    oc = orc.OracleCache(cache, [-0.5, 0.0, 0.5], 16)
+    ox, od, og, ob, ot = orc.train_batch(42, 17, n, oc, float(cache.max()), g_sampling="uniform")
+    np.testing.assert_array_equal(xyz.astype(np.float64), ox)
+    assert np.abs(dirs - od).max() < 2e-6
+    dg = np.abs(g - og)
+    say("  g max |d|", dg.max(), "range", g.min(), g.max())
+    assert dg.max() <= 2.0 ** -22
+    # a g within rounding of a bin boundary may take the other neighbour (same target)
+    near = np.abs(og[:, None] - np.array([0.0])[None, :]).min(axis=1) < 1e-6
+    np.testing.assert_array_equal(b[~near], ob[~near])
+    d = np.abs(tgt - ot)
+    say("  target max |d|", d.max())
+    assert d.max() < 3e-7
+
+
+def _relu_safe_samples(orc, desc, L, p, n, seed, floor=1e-6):
+    """n query samples (x, w, g) at which no hidden ReLU of the FP64 oracle's field changes
+    state when a direction coordinate moves by up to the FP32 coordinate error
+    (DIR_COORD_EPS), and every pre-activation is at least `floor` from zero.  A ReLU that flips
+    switches its whole delta on or off, so a sample at a kink moves the gradient by a finite
+    amount under any rounding-level change of the encoding; away from kinks the gradient is
+    continuous in the encoding and a bar can be derived from a perturbation."""
+    rng = np.random.default_rng(seed)
+    W = [np.asarray(p[L.w_off[m]:L.w_off[m] + L.w_rows[m] * L.w_cols[m]], dtype=np.float64)
+         .reshape(L.w_rows[m], L.w_cols[m]) for m in range(L.n_mats)]
+
+    def pre_acts(x, w, g):
+        h = np.stack([orc.field_encode(desc, p, x[i], w[i], float(g[i])) for i in range(len(x))])
+        out = []
+        for M in W[:-1]:
+            pre = h @ M.T
+            out.append(pre)
+            h = np.maximum(pre, 0.0)
+        return np.concatenate(out, axis=1)
+
+    xs, ws, gs = [], [], []
+    got = 0
+    for _ in range(20):
+        m = 2 * n
+        x = rng.uniform(size=(m, 3)).astype(np.float32)
+        w = rng.normal(size=(m, 3))
+        w = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
+        g = rng.uniform(-0.8, 0.8, m).astype(np.float32)
+        base = pre_acts(x, w, g)
+        ok = np.abs(base).min(axis=1) >= floor
+        for _, _, d in coord_moves(w):
+            ok &= np.all(np.signbit(pre_acts(x, d, g)) == np.signbit(base), axis=1)
+        xs.append(x[ok])
+        ws.append(w[ok])
+        gs.append(g[ok])
+        got += int(ok.sum())
+        if got >= n:
+            return (np.concatenate(xs)[:n], np.concatenate(ws)[:n], np.concatenate(gs)[:n])
+    raise AssertionError(f"only {got} of {n} kink-free samples")
+
+
+def _segments(L, feats=2):
+    """Every grid level of both grids (dense levels marked d, hashed h) and every weight
+    matrix, as parameter ranges."""
+    segs = {}
+    levels = (L.n_in - 1) // (2 * feats)
+    for l in range(levels):
+        segs[f"pos{l}{'d' if L.pos_dense[l] else 'h'}"] = (feats * L.pos_off[l],
+                                                           feats * L.pos_off[l + 1])
+    for l in range(levels):
+        segs[f"dir{l}{'d' if L.dir_dense[l] else 'h'}"] = (L.pos_params + feats * L.dir_off[l],
+                                                           L.pos_params + feats * L.dir_off[l + 1])
     for m in range(L.n_mats):
         segs[f"W{m}"] = (L.w_off[m], L.w_off[m] + L.w_rows[m] * L.w_cols[m])
     return segs
 
 
-@pytest.mark.parametrize("levels,hidden", [(16, 3), (8, 2), (16, 1)])
-def test_forward_backward_gradients(orc, tctx, levels, hidden):
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("levels,hidden,log2_table", [(16, 3, 12), (8, 2, 12), (16, 1, 12),
+                                                     (16, 3, 19)])
+def test_forward_backward_gradients(orc, tctx, levels, hidden, log2_table):
+    """Loss and gradient of every grid level and weight matrix against the oracle.  With
+    T = 2^19 (the benchmark's table) position levels 0-3 and direction levels 0-9 are dense, so
+    both scatter branches are compared level by level."""
     import torch
     from paper_2304_07338_amd.pfn import FieldConfig
     ctx, _ = tctx
-    cfg = FieldConfig(levels=levels, hidden_layers=hidden, log2_table=12)
+    cfg = FieldConfig(levels=levels, hidden_layers=hidden, log2_table=log2_table)
     desc = odesc(orc, cfg)
     ctx.field_select(1)
     ctx.field_init(cfg, seed=1)
     p, L = _random_params(orc, desc, seed=levels * 10 + hidden)
     ctx.field_set_params(torch.tensor(p, device="cuda:0"))
     n = 16 * 40 + 7
-    rng = np.random.default_rng(3)
-    x = rng.uniform(size=(n, 3)).astype(np.float32)
-    w = rng.normal(size=(n, 3))
-    w = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
-    g = rng.uniform(-0.8, 0.8, n).astype(np.float32)
-    tgt = rng.uniform(0, 1, (n, 3)).astype(np.float32)
-    dev = [torch.tensor(a, device="cuda:0") for a in (x, w, g, tgt)]
     pd = p.astype(np.float64)
+    x, w, g = _relu_safe_samples(orc, desc, L, pd, n, seed=3)
+    tgt = np.random.default_rng(13).uniform(0, 1, (n, 3)).astype(np.float32)
+    dev = [torch.tensor(a, device="cuda:0") for a in (x, w, g, tgt)]
+    segs = _segments(L)
+    if log2_table == 19 and levels == 16:
+        assert [k for k in segs if k.startswith("pos") and k.endswith("d")] == \
+            ["pos0d", "pos1d", "pos2d", "pos3d"]
     for prec, rounding in (("f32", 0), ("f16", 1), ("bf16", 2)):
         loss, grad = ctx.field_forward_backward(*dev, precision=prec)
         grad = grad.cpu().numpy().astype(np.float64)
         oloss, ograd = orc.field_loss_grad(desc, pd, x, w, g, tgt, rounding=rounding)
         say(f"  {prec}: loss {loss:.6e} vs {oloss:.6e}")
-        for name, (a0, a1) in _segments(L).items():
+        if prec == "f32":
+            # the oracle's own change when the direction coordinates move by the FP32
+            # coordinate error (random signs per sample)
+            jloss, jgrad = orc.field_loss_grad(desc, pd, x, coord_jitter(w, seed=5), g, tgt)
+        worst = 0.0
+        for name, (a0, a1) in segs.items():
             gg, og = grad[a0:a1], ograd[a0:a1]
-            rel = np.linalg.norm(gg - og) / max(np.linalg.norm(og), 1e-300)
+            rel = _rel(gg, og)
             cos = gg @ og / max(np.linalg.norm(gg) * np.linalg.norm(og), 1e-300)
-            say(f"    {name:8s} rel-L2 {rel:.2e} cos {cos:.6f}")
             if prec == "f32":
-                assert rel <= 1e-5, name
+                sens = _rel(jgrad[a0:a1], og)
+                bar = 1e-5 + 1.5 * sens
+                say(f"    {name:6s} rel-L2 {rel:.2e} (bar {bar:.2e}) cos {cos:.8f}")
+                worst = max(worst, rel / bar)
+                assert rel <= bar, name
             else:
+                say(f"    {name:6s} rel-L2 {rel:.2e} cos {cos:.6f}")
                 # activations and deltas are rounded to 16 bits after every product (relative
                 # 2^-11 for f16, 2^-8 for bf16) along a chain of 2H+1 products
                 tol_rel, tol_cos = (4e-2, 0.999) if prec == "f16" else (1.5e-1, 0.99)
                 assert rel <= tol_rel and cos >= tol_cos, name
         if prec == "f32":
-            assert loss == pytest.approx(oloss, rel=1e-6)
+            say(f"    worst rel/bar {worst:.3f}")
+            assert abs(loss - oloss) <= 1e-6 * oloss + 2.0 * abs(jloss - oloss)
         else:
             assert loss == pytest.approx(oloss, rel=2e-2)
 
@@ -122,22 +213,22 @@ def test_relative_loss_gradients(orc, tctx, hidden, growth, levels):
     p, L = _random_params(orc, desc, seed=70 + hidden)
     ctx.field_set_params(torch.tensor(p, device="cuda:0"))
     n = 16 * 30 + 5
-    rng = np.random.default_rng(4)
-    x = rng.uniform(size=(n, 3)).astype(np.float32)
-    w = rng.normal(size=(n, 3))
-    w = (w / np.linalg.norm(w, axis=1, keepdims=True)).astype(np.float32)
-    g = rng.uniform(-0.8, 0.8, n).astype(np.float32)
-    tgt = rng.uniform(0, 1, (n, 3)).astype(np.float32)
+    x, w, g = _relu_safe_samples(orc, desc, L, p.astype(np.float64), n, seed=4)
+    tgt = np.random.default_rng(14).uniform(0, 1, (n, 3)).astype(np.float32)
     dev = [torch.tensor(a, device="cuda:0") for a in (x, w, g, tgt)]
     loss, grad = ctx.field_forward_backward(*dev, precision="f32", loss="rel")
     grad = grad.cpu().numpy().astype(np.float64)
     oloss, ograd = orc.field_loss_grad(desc, p.astype(np.float64), x, w, g, tgt, loss="rel")
     say(f"  relative L2, {hidden} hidden, growth {growth}: loss {loss:.6e} vs {oloss:.6e}")
     assert loss == pytest.approx(oloss, rel=1e-5)
+    _, jgrad = orc.field_loss_grad(desc, p.astype(np.float64), x, coord_jitter(w, seed=6), g,
+                                   tgt, loss="rel")
     for name, (a0, a1) in _segments(L).items():
         gg, og = grad[a0:a1], ograd[a0:a1]
-        rel = np.linalg.norm(gg - og) / max(np.linalg.norm(og), 1e-300)
-        assert rel <= 2e-5, name
+        rel = _rel(gg, og)
+        bar = 2e-5 + 1.5 * _rel(jgrad[a0:a1], og)
+        say(f"    {name:6s} rel-L2 {rel:.2e} (bar {bar:.2e})")
+        assert rel <= bar, name
     ctx.field_select(0)
 
 
@@ -161,7 +252,7 @@ def test_adam_step_matches_oracle(orc, tctx):
     gp = ctx.field_get_params().cpu().numpy().astype(np.float64)
     err = np.abs(gp - p).max()
     say("  adam max |dp|", err, "step size", np.abs(p - p0).max())
-    assert err <= 1e-6 * max(1.0, np.abs(p).max())
+    assert err <= 3e-7 * max(1.0, np.abs(p).max())  # measured 3e-8
 
 
 def test_training_fits_a_smooth_target(orc, tctx):

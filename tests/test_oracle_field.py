@@ -300,6 +300,39 @@ def test_training_batch_distribution_and_targets(orc):
     np.testing.assert_array_equal(xyz3, xyz[:10])
 
 
+def test_uniform_g_batch_pins(orc):
+    """Batches with g uniform over [g_0, g_last] (targets interpolated linearly in g): the same
+    positions and directions as pool batches (the same draws), g mapping back to the pool's bin
+    draw, a uniform distribution of g, and closed-form targets for a cache that is constant in
+    space and linear in g (so that linear interpolation between bins is exact)."""
+    res = 4
+    gb = [-0.75, -0.1, 0.3, 0.8]
+    alpha = np.array([0.5, 0.3, 0.2])
+    beta = np.array([0.2, -0.1, 0.15])
+    data = np.zeros((4, res, res, res, 3))
+    for b, gv in enumerate(gb):
+        data[b] = alpha + beta * gv
+    cache = orc.OracleCache(data, gb, res)
+    kappa = 0.9
+    n = 40000
+    px, pd, pg, pb, _ = orc.train_batch(77, 3, n, cache, kappa)
+    ux, ud, ug, ub, ut = orc.train_batch(77, 3, n, cache, kappa, g_sampling="uniform")
+    np.testing.assert_array_equal(ux, px)
+    np.testing.assert_array_equal(ud, pd)
+    assert ug.min() > gb[0] and ug.max() < gb[-1]
+    # the uniform draw behind both: u = (g - g0) / (g_last - g0) gives the pool's bin floor(u n)
+    u = (ug - gb[0]) / (gb[-1] - gb[0])
+    np.testing.assert_array_equal(np.minimum(np.floor(u * 4).astype(int), 3), pb)
+    from scipy import stats
+    assert stats.kstest(u, "uniform").pvalue > 1e-3
+    # reported bin: the lower neighbour of g
+    edges = np.array(gb)
+    np.testing.assert_array_equal(ub, np.clip(np.searchsorted(edges, ug, side="right") - 1, 0, 2))
+    # closed form: the cache value at g is alpha + beta g
+    want = np.array([[orc.log_encode(v / kappa, 5.0) for v in alpha + beta * gg] for gg in ug[:500]])
+    np.testing.assert_allclose(ut[:500], want, rtol=1e-13, atol=1e-15)
+
+
 def stats_chi_ok(counts):
     from scipy import stats
     return stats.chisquare(counts).pvalue > 1e-3
