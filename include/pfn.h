@@ -317,6 +317,17 @@ pfn_status pfn_render_path_traced(pfn_context *ctx, const pfn_camera *cam, int s
  * Synchronises. */
 pfn_status pfn_image_error(pfn_context *ctx, const float *dev_img, const float *dev_ref, int64_t n,
                            double *host_rmse, double *host_rel_rmse, double *host_psnr);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * or evaluation loops, harnesses that forbid hipMalloc): the same three figures as
+ * pfn_image_error, with no allocation of any kind and no synchronisation.  dev_result receives
+ * (RMSE, RMSE / mean(ref), PSNR) as 3 doubles in device memory, ready in stream order.  The
+ * FP64 partial sums live in a fixed device array of the library (64 KiB on each GPU it runs on,
+ * held until the process ends): per-block partials, then one block adds them in a fixed order, so
+ * results are bit-reproducible.  n is limited to 2048 * 256 * 64 = 33,554,432 values
+ * (PFN_ERR_INVALID_ARG beyond, and for n < 1 or NULL pointers).  All calls on one GPU share the
+ * array: calls that overlap on one GPU (other streams, contexts or threads) race. */
+pfn_status pfn_image_error_noalloc(pfn_context *ctx, const float *dev_img, const float *dev_ref,
+                                   int64_t n, double *dev_result);
 
 /* Tile shape of the ray-march launch: each wave covers tile_w x (64 / tile_w) pixels and a
  * workgroup block_w x block_h waves (block_w * block_h = 4).  Chosen by the autotuner. */

@@ -118,6 +118,7 @@ SIGNATURES = {
                                          C.c_int, C.c_int, C.c_uint64, vp]),
     "pfn_image_error": (C.c_int, [ctxp, vp, vp, C.c_int64, C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "pfn_image_error_noalloc": (C.c_int, [ctxp, vp, vp, C.c_int64, vp]),
     "pfn_set_tile_config": (C.c_int, [ctxp, C.c_int, C.c_int, C.c_int]),
     "pfn_set_launch_mode": (C.c_int, [ctxp, C.c_int, C.c_int]),
     "pfn_set_render_strategy": (C.c_int, [ctxp, C.c_int]),

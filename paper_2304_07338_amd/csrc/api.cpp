@@ -111,6 +111,11 @@ extern "C" pfn_status pfn_create(int device, void *hip_stream, pfn_context **out
   if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return PFN_ERR_HIP;
   if (device < 0 || device >= n) return PFN_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return PFN_ERR_HIP;
+  // once per device: the device address of pfn_image_error_noalloc's fixed scratch array
+  if (pfn_noalloc_init(device) != hipSuccess) {
+    (void)hipGetLastError();
+    return PFN_ERR_HIP;
+  }
   pfn_context *ctx = new (std::nothrow) pfn_context();
   if (!ctx) return PFN_ERR_OUT_OF_MEMORY;
   ctx->device = device;

@@ -217,6 +217,9 @@ pfn_status pfn_hip(pfn_context *ctx, hipError_t e, const char *what);
   } while (0)
 
 pfn_status ensure_scratch(pfn_context *ctx, size_t bytes);
+// Resolves (once per device, with that device current) the device address of the fixed scratch
+// array behind pfn_image_error_noalloc.
+hipError_t pfn_noalloc_init(int device);
 pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<MarchJob> &mj,
                          int direct, int prec, int slot, const FieldDev &fd_host, bool overlap);
 void wf_release(WfState &w);

@@ -6,6 +6,9 @@
 // point light with a ratio-tracking transmittance estimate; the throughput takes the albedo and
 // the direction is resampled from HG(g); at most max_bounces collisions, optional Russian
 // roulette.  Black background.  Samples are split over launches so that no launch runs long.
+#include <mutex>
+#include <string>
+
 #include "pfn_ctx.h"
 
 #define PT_THREADS 256
@@ -245,5 +248,126 @@ extern "C" pfn_status pfn_image_error(pfn_context *ctx, const float *img, const 
   if (rmse) *rmse = r;
   if (rel) *rel = r / (h[1] / (double)n);
   if (psnr) *psnr = 20.0 * std::log10((double)m / r);
+  return PFN_OK;
+}
+
+// ------------------------------------------------------------------ error reduction without allocation
+// pfn_image_error_noalloc keeps its partial sums in this fixed device array instead of a
+// context buffer.  Host code never uses the array's name as an address: each device's copy is
+// resolved once with hipGetSymbolAddress (pfn_noalloc_init, called by pfn_create with the device
+// current) and that pointer is what the kernels receive.
+#define NOALLOC_MAX_BLOCKS 2048
+#define NOALLOC_ITEMS 64  // values per thread of the partial-sum kernel
+static __device__ __align__(256) double scratch[NOALLOC_MAX_BLOCKS * 4];
+
+#define NOALLOC_MAX_DEVICES 64
+static std::mutex g_noalloc_mu;
+static void *g_noalloc_ptr[NOALLOC_MAX_DEVICES];
+
+hipError_t pfn_noalloc_init(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[device]) return hipSuccess;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_noalloc_ptr[device] = p;
+  return hipSuccess;
+}
+
+// Per block: sum of squared differences, sum of the reference and its maximum over the block's
+// 256 * NOALLOC_ITEMS values (written, not accumulated: nothing needs clearing).
+__global__ __launch_bounds__(256) void image_error_partial_kernel(const float *__restrict__ img,
+                                                                  const float *__restrict__ ref,
+                                                                  int64_t n, double *part) {
+  __shared__ double sse[4], ssr[4];
+  __shared__ float smx[4];
+  double se = 0.0, sr = 0.0;
+  float m = 0.0f;
+  const int64_t base = (int64_t)blockIdx.x * (256 * NOALLOC_ITEMS) + threadIdx.x;
+  for (int k = 0; k < NOALLOC_ITEMS; ++k) {
+    const int64_t i = base + (int64_t)k * 256;
+    if (i < n) {
+      const double d = (double)img[i] - (double)ref[i];
+      se += d * d;
+      sr += (double)ref[i];
+      m = fmaxf(m, ref[i]);
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    se += __shfl_down(se, off);
+    sr += __shfl_down(sr, off);
+    m = fmaxf(m, __shfl_down(m, off));
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sse[w] = se;
+    ssr[w] = sr;
+    smx[w] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* o = part + 4 * (size_t)blockIdx.x;
+    o[0] = (sse[0] + sse[1]) + (sse[2] + sse[3]);
+    o[1] = (ssr[0] + ssr[1]) + (ssr[2] + ssr[3]);
+    o[2] = (double)fmaxf(fmaxf(smx[0], smx[1]), fmaxf(smx[2], smx[3]));
+    o[3] = 0.0;
+  }
+}
+
+// One block adds the partials in a fixed order and writes (RMSE, RMSE / mean(ref), PSNR).
+__global__ __launch_bounds__(256) void image_error_final_kernel(const double *part, int nblocks,
+                                                                int64_t n, double *result) {
+  __shared__ double sse[256], ssr[256], smx[256];
+  double se = 0.0, sr = 0.0, m = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+    se += part[4 * b];
+    sr += part[4 * b + 1];
+    m = fmax(m, part[4 * b + 2]);
+  }
+  sse[threadIdx.x] = se;
+  ssr[threadIdx.x] = sr;
+  smx[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sse[threadIdx.x] += sse[threadIdx.x + s];
+      ssr[threadIdx.x] += ssr[threadIdx.x + s];
+      smx[threadIdx.x] = fmax(smx[threadIdx.x], smx[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double r = sqrt(sse[0] / (double)n);
+    result[0] = r;
+    result[1] = r / (ssr[0] / (double)n);
+    result[2] = 20.0 * log10(smx[0] / r);
+  }
+}
+
+extern "C" pfn_status pfn_image_error_noalloc(pfn_context *ctx, const float *img, const float *ref,
+                                              int64_t n, double *dev_result) {
+  if (!ctx) return PFN_ERR_INVALID_ARG;
+  if (!img || !ref || !dev_result || n < 1)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG, "bad image arguments");
+  const int64_t max_n = (int64_t)NOALLOC_MAX_BLOCKS * 256 * NOALLOC_ITEMS;
+  if (n > max_n)
+    return pfn_fail(ctx, PFN_ERR_INVALID_ARG,
+                    "n exceeds the no-allocation limit of " + std::to_string(max_n) + " values");
+  void *p = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (ctx->device >= 0 && ctx->device < NOALLOC_MAX_DEVICES) p = g_noalloc_ptr[ctx->device];
+  }
+  if (!p) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no-allocation scratch not resolved");
+  PFN_HIP(ctx, hipSetDevice(ctx->device));
+  double *part = (double *)p;
+  const int nblocks = (int)((n + 256 * NOALLOC_ITEMS - 1) / (256 * NOALLOC_ITEMS));
+  hipLaunchKernelGGL(image_error_partial_kernel, dim3((unsigned)nblocks), dim3(256), 0,
+                     ctx->stream, img, ref, n, part);
+  PFN_HIP(ctx, hipGetLastError());
+  hipLaunchKernelGGL(image_error_final_kernel, dim3(1), dim3(256), 0, ctx->stream, part, nblocks,
+                     n, dev_result);
+  PFN_HIP(ctx, hipGetLastError());
   return PFN_OK;
 }

@@ -462,6 +462,15 @@ class Context:
                                           C.byref(rm), C.byref(rel), C.byref(ps)))
         return rm.value, rel.value, ps.value
 
+    def image_error_noalloc(self, img, ref, out):
+        """The same figures into `out` (3 float64 on the device), with no allocation and no
+        synchronisation (pfn_image_error_noalloc)."""
+        import torch
+        _check(out, torch.float64, 3, "out")
+        self._ok(self.lib.pfn_image_error_noalloc(self.h, _ptr(img), _ptr(ref), img.numel(),
+                                                  _ptr(out)))
+        return out
+
     # ------------------------------------------------------------------ tuning / timing
     def set_tile_config(self, tile_w: int, block_w: int, block_h: int):
         self._ok(self.lib.pfn_set_tile_config(self.h, tile_w, block_w, block_h))
