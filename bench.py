@@ -77,6 +77,12 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "fused", "wavefront", "wavefront_serial"],
                     help="form of the field-lit render")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the precision / spp / g / direct-light variants of the frame")
+    ap.add_argument("--no-matched", action="store_true",
+                    help="skip the matched-RMSE comparison with the path tracer on the frame")
+    ap.add_argument("--mr2-ref-spp", type=int, default=1024,
+                    help="reference spp of the matched-RMSE comparison on the benchmark frame")
     ap.add_argument("--matched-rmse", action="store_true",
                     help="run the large-scale comparison with the path tracer instead")
     ap.add_argument("--mr-n", type=int, default=1024, help="volume side of the comparison")
@@ -242,6 +248,8 @@ def main():
     cache_ms = (time.perf_counter() - tc0) * 1000.0 / n_cache
 
     fi_info = None if args.no_first_interaction else first_interaction_bench(ctx, cam, rc, args)
+    variants = None if args.no_variants else frame_variants(ctx, cam, rc, out, args)
+    matched = None if args.no_matched else matched_rmse_frame(ctx, cam, rc, out, ms_per_step, args)
 
     result = {
         "metric": "1080p fps + field queries/s: photon field vs path tracer at matched RMSE",
@@ -264,11 +272,7 @@ def main():
         "field_queries_per_frame": int(queries_f),
         "march_steps_per_frame": int(steps_f),
         "cache_gather_fps": round(1000.0 / cache_ms, 3),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": measured_traffic(dom) if args.precision == "f16" else None,
-                     "kernel": dom, "kernel_ms_per_frame": round(dom_ms, 4),
-                     "algorithmic_bytes_per_frame": int(dom_bytes)},
+        "roofline": roofline_entry(dom, dom_bytes, dom_ms, achieved, args),
         "frame": {"gpu_ms": round(frame_ms, 4), "algorithmic_bytes": int(bytes_frame),
                   "GB_s": round(bytes_frame / (frame_ms * 1e-3) / 1e9, 2),
                   "strategy": "wavefront" if kernels else "fused", "kernels": kernels},
@@ -279,6 +283,10 @@ def main():
         "image_mean": img_mean,
     }
 
+    if matched is not None:
+        result["matched_rmse"] = matched
+    if variants is not None:
+        result["variants"] = variants
     if fi_info is not None:
         result["first_interaction"] = fi_info
     if not args.no_photon_map:
@@ -291,6 +299,166 @@ def main():
 
     print(json.dumps(result), flush=True)
     ctx.close()
+
+
+def address_record(kernel):
+    """The address-path record of `kernel` from the committed counter summaries (texture
+    addresser busy fraction with the kernel alone on the chip, and the probe's ceilings), or
+    None when there is none or the kernel sources have changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.md"))):
+        with open(path) as f:
+            for l in f:
+                if l.startswith("address-record:"):
+                    r = json.loads(l.split(":", 1)[1])
+                    if r["kernel"].split("<")[0] != kernel:
+                        continue
+                    h = hashlib.sha256()
+                    for name in r["sources"]:
+                        with open(os.path.join(ROOT, "paper_2304_07338_amd", "csrc", name), "rb") as g:
+                            h.update(g.read())
+                    return r if h.hexdigest() == r["sources_sha256"] else None
+    return None
+
+
+def roofline_entry(kernel, alg_bytes, kernel_ms, achieved, args):
+    """Roofline row of the frame's dominant kernel: algorithmic bytes per frame over its
+    event-timed duration per frame (it shares the chip with the other rounds' kernels), against
+    8 TB/s; the calibrated HBM traffic of its launches and that traffic's rate; and its binding
+    ceiling, the vector-memory address path, with the addresser's busy fraction measured by
+    counters."""
+    traffic = measured_traffic(kernel) if args.precision == "f16" else None
+    r = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic, "kernel": kernel,
+         "kernel_ms_per_frame": round(kernel_ms, 4), "algorithmic_bytes_per_frame": int(alg_bytes)}
+    if traffic is not None:
+        gbs = traffic / (kernel_ms * 1e-3) / 1e9
+        r["traffic_GB_s"] = round(gbs, 1)
+        r["traffic_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    rec = address_record(kernel) if args.precision == "f16" else None
+    if rec is not None:
+        r["binding"] = {"ceiling": "vector-memory address path (one lane address per CU clock)",
+                        "counter": "TA_TA_BUSY", "busy_frac": rec["ta_busy_frac"],
+                        "probe_lanes_per_cu_clock": rec["address_ceiling_lanes_per_cu_clock"]}
+    return r
+
+
+def _timed_frames(ctx, cam, cfg, out, reps):
+    import torch
+    ctx.render_frame(cam, cfg, out)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(reps):
+        ctx.render_frame(cam, cfg, out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - ts) * 1000.0 / reps
+
+
+def frame_variants(ctx, cam, rc, out, args):
+    """The benchmark frame with one setting changed at a time: the field's arithmetic (BF16
+    matrix cores, FP32), samples per pixel (2, 4, 8), g between the trained bins (0.2), and the
+    direct light from exact shadow rays instead of the light-transmittance volume (on a 256x256
+    frame of the same view, where the shadow rays are affordable), with the relative RMSE
+    between the two direct-light forms (the light volume's bias)."""
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd.pfn import RenderConfig, DIRECT_SHADOW_RAYS
+    res = {"field_precision": {}, "spp": {}, "g": {}}
+    reps = 5
+    for prec in ("bf16", "f32"):
+        ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "field_precision": prec}),
+                           out, reps)
+        res["field_precision"][prec] = {"ms_per_frame": round(ms, 3), "fps": round(1000 / ms, 3)}
+        log(f"[variants] field {prec}: {ms:.2f} ms")
+    for spp in (2, 4, 8):
+        ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "spp": spp, "seed": 5}), out,
+                           reps)
+        res["spp"][str(spp)] = {"ms_per_frame": round(ms, 3), "fps": round(1000 / ms, 3)}
+        log(f"[variants] {spp} spp: {ms:.2f} ms")
+    ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "g": 0.2}), out, reps)
+    res["g"]["0.2"] = {"ms_per_frame": round(ms, 3), "fps": round(1000 / ms, 3)}
+    log(f"[variants] g 0.2: {ms:.2f} ms")
+    small = sg.Camera(cam.eye, cam.target, cam.up, cam.fov_y_deg, 256, 256)
+    o_lv = torch.empty((256, 256, 3), dtype=torch.float32, device="cuda:0")
+    o_sr = torch.empty_like(o_lv)
+    ms_lv = _timed_frames(ctx, small, rc, o_lv, 3)
+    ms_sr = _timed_frames(ctx, small, RenderConfig(**{**rc.__dict__, "direct": DIRECT_SHADOW_RAYS}),
+                          o_sr, 3)
+    e = ctx.image_error(o_lv, o_sr)
+    res["direct_light_256x256"] = {"light_volume_ms": round(ms_lv, 3),
+                                   "shadow_rays_ms": round(ms_sr, 3),
+                                   "light_volume_rel_rmse_vs_shadow_rays": e[1],
+                                   "light_volume_psnr_vs_shadow_rays": e[2]}
+    log(f"[variants] 256x256 light volume {ms_lv:.2f} ms vs shadow rays {ms_sr:.2f} ms, "
+        f"rel-RMSE {e[1]:.4g}")
+    return res
+
+
+def matched_rmse_frame(ctx, cam, rc, out, field_ms, args):
+    """The benchmark frame against the Monte Carlo path tracer at equal error (the comparison
+    of Section 4.3.1, on this GPU): a path-traced reference of --mr2-ref-spp samples (8 bounces,
+    HG sampling, Russian roulette from bounce 3), the field frame as timed (1 spp), the plain
+    cache gather, and the path tracer at 16..256 spp.  The path tracer's squared error is fitted
+    as c^2 (1/spp + 1/ref_spp), solved for the spp at which it equals the field's, and its time
+    interpolated there; the speedup is that time over the field frame's."""
+    import numpy as np
+    import torch
+    from paper_2304_07338_amd.pfn import RenderConfig, INDIRECT_CACHE
+    g = rc.g
+    chunk = min(256, args.mr2_ref_spp)
+    n_chunks = max(1, args.mr2_ref_spp // chunk)
+    ref = torch.zeros_like(out)
+    part = torch.empty_like(out)
+    for c in range(n_chunks):
+        ctx.render_path_traced(cam, chunk, max_bounces=8, g=g, rr_start=3, seed=3000 + c,
+                               out=part)
+        ref += part
+        torch.cuda.synchronize()
+    ref /= n_chunks
+    log(f"[matched] reference {n_chunks * chunk} spp done")
+    ctx.render_frame(cam, rc, out)
+    e_field = ctx.image_error(out, ref)
+    cache_ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "indirect": INDIRECT_CACHE}),
+                             out, 3)
+    e_cache = ctx.image_error(out, ref)
+    pt_spp = [16, 32, 64, 128, 256]
+    pts = []
+    img = torch.empty_like(out)
+    for spp in pt_spp:
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        ctx.render_path_traced(cam, spp, max_bounces=8, g=g, rr_start=3, seed=4000 + spp, out=img)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ts) * 1000.0
+        pts.append((spp, ms, ctx.image_error(img, ref)[0]))
+        log(f"[matched] path tracer {spp} spp: {ms:.1f} ms, RMSE {pts[-1][2]:.4g}")
+    spp_a = np.array([p[0] for p in pts], dtype=np.float64)
+    t_a = np.array([p[1] for p in pts])
+    e_a = np.array([p[2] for p in pts])
+    ref_spp = n_chunks * chunk
+    basis = 1.0 / spp_a + 1.0 / ref_spp
+    c2 = float(np.sum(e_a ** 2 * basis) / np.sum(basis ** 2))
+    slope, icpt = np.polyfit(spp_a, t_a, 1)
+    inv = e_field[0] ** 2 / c2 - 1.0 / ref_spp
+    spp_star = speedup = None
+    if inv <= 0:
+        note = "the field's error is below the reference's own noise"
+    else:
+        spp_star = 1.0 / inv
+        note = ("interpolated" if pt_spp[0] <= spp_star <= pt_spp[-1] else
+                "extrapolated above 256 spp" if spp_star > pt_spp[-1] else
+                "the path tracer reaches the field's error below 16 spp")
+        speedup = max(icpt + slope * spp_star, 0.0) / field_ms
+    log(f"[matched] field RMSE {e_field[0]:.4g}, cache {e_cache[0]:.4g}; matched spp {spp_star} "
+        f"({note}), speedup {speedup}")
+    return {"g": g, "reference_spp": ref_spp,
+            "field": {"ms": round(field_ms, 3), "rmse": e_field[0], "rel_rmse": e_field[1],
+                      "psnr": e_field[2]},
+            "cache_gather": {"ms": round(cache_ms, 3), "rmse": e_cache[0], "rel_rmse": e_cache[1],
+                             "psnr": e_cache[2]},
+            "path_tracer": [{"spp": p[0], "ms": round(p[1], 3), "rmse": p[2]} for p in pts],
+            "spp_matched": spp_star, "note": note, "speedup_at_matched_rmse": speedup}
 
 
 def first_interaction_bench(ctx, cam, rc, args):

@@ -3,10 +3,12 @@ field every 4 steps, FP16 matrix cores) a few times, plus one plain device copy 
 memory counters calibrate the HBM traffic counters.  The field keeps its initial parameters:
 the memory access pattern of a ray-marched frame does not depend on the parameter values.
 With --renderer first_interaction it renders the same view with the Algorithm 2 renderer at 1
-spp instead (at --width x --height).
+spp instead (at --width x --height).  With --train-steps N it then runs N training steps of the
+benchmark's recipe (batch 2^18, FP16 matrix cores) on the traced cache, for the training kernels'
+counters.
 
     python -m paper_2304_07338_amd.profile_run [--frames 3] [--strategy auto|fused|wavefront]
-        [--renderer march|first_interaction] [--width 1920 --height 1080]
+        [--renderer march|first_interaction] [--width 1920 --height 1080] [--train-steps 0]
 """
 import argparse
 import os
@@ -26,12 +28,13 @@ def main():
     ap.add_argument("--renderer", default="march", choices=["march", "first_interaction"])
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--train-steps", type=int, default=0)
     args = ap.parse_args()
     import torch
     from paper_2304_07338_amd import scenegen as sg
     from paper_2304_07338_amd import workloads as wl
-    from paper_2304_07338_amd.pfn import (Context, FieldConfig, RenderConfig, DIRECT_LIGHT_VOLUME,
-                                          INDIRECT_FIELD)
+    from paper_2304_07338_amd.pfn import (Context, FieldConfig, RenderConfig, TrainConfig,
+                                          DIRECT_LIGHT_VOLUME, INDIRECT_FIELD)
     w = wl.C2
     vol, tf, lights = wl.make_scene(w, device="cuda:0")
     ctx = Context(0)
@@ -54,6 +57,10 @@ def main():
         render(cam, rc, out)
         torch.cuda.synchronize()
         print(f"frame {i} done", flush=True)
+    if args.train_steps > 0:
+        ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, precision="f16",
+                                    seed=7))
+        print(f"{args.train_steps} training steps done", flush=True)
     src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
