@@ -392,6 +392,46 @@ def frame_variants(ctx, cam, rc, out, args):
                                    "light_volume_psnr_vs_shadow_rays": e[2]}
     log(f"[variants] 256x256 light volume {ms_lv:.2f} ms vs shadow rays {ms_sr:.2f} ms, "
         f"rel-RMSE {e[1]:.4g}")
+    res["paper_encoding"] = paper_encoding_costs(ctx, cam, rc, out, reps)
+    return res
+
+
+def paper_encoding_costs(ctx, cam, rc, out, reps):
+    """The paper's encoding and network (Section 3.4: 16 levels x 8 features, growth 2, table
+    2^19, 5 hidden layers) in a field slot of its own: the benchmark frame lit by it, and
+    training steps of the paper's recipe (batches of 2^16, relative L2, Section 3.5.1) beside
+    steps of the configuration's recipe on the same field.  The march, query count and launch
+    shapes do not depend on the parameter values, so the field is trained for the timing only."""
+    import torch
+    from paper_2304_07338_amd.pfn import FieldConfig, PfnError, RenderConfig, TrainConfig
+    slot = (rc.field_slot + 1) % 8
+    fc = FieldConfig(levels=16, feats_per_level=8, growth=2.0, log2_table=19, hidden_layers=5)
+    ctx.field_select(slot)
+    ctx.field_init(fc, seed=5)
+    res = {"field": {"levels": 16, "feats_per_level": 8, "growth": 2.0, "log2_table": 19,
+                     "hidden_layers": 5, "n_params": ctx.field_num_params()}}
+    try:
+        for name, tc in (("paper_recipe", TrainConfig(steps=100, log2_batch=16, loss="rel",
+                                                      seed=5)),
+                         ("batch_2p18_l2", TrainConfig(steps=50, log2_batch=18, seed=5))):
+            ctx.train_field(TrainConfig(**{**tc.__dict__, "steps": 3}))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.train_field(tc)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0 / tc.steps
+            res[f"train_{name}"] = {"batch": 1 << tc.log2_batch, "loss": tc.loss,
+                                    "ms_per_step": round(ms, 3)}
+            log(f"[variants] paper encoding, training {name}: {ms:.3f} ms per step")
+        try:
+            ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "field_slot": slot}),
+                               out, reps)
+            res["frame"] = {"ms_per_frame": round(ms, 3), "fps": round(1000 / ms, 3)}
+            log(f"[variants] paper encoding frame: {ms:.2f} ms")
+        except PfnError as e:  # the fused strategy renders 2-feature fields only
+            res["frame"] = str(e)
+    finally:
+        ctx.field_select(rc.field_slot)
     return res
 
 
@@ -822,11 +862,16 @@ def studies(args):
     """Phase-function awareness and stochastic noise (Sections 4.3 and 4.5 of the paper), on the
     256^3 f32 synthetic scene with 3 lights at 640x480.
 
-    Phase awareness: a field trained on a trace with G = {-0.75, 0, 0.75} renders L_i (the
-    field-lit ray-marched frame minus the direct-only frame) at g in {-0.75, -0.35, 0, 0.35,
+    Phase awareness: fields trained on a trace with G = {-0.75, 0, 0.75}, one with g drawn from
+    G and one with g uniform in [-0.75, 0.75] (targets linear in g between the bins), render L_i
+    (the field-lit ray-marched frame minus the direct-only frame) at g in {-0.75, -0.35, 0, 0.35,
     0.75}; each is compared with the L_i of a separate single-bin photon cache traced at exactly
-    that g (so g = +-0.35 are phases the field never saw).  The error between two independent
-    reference traces at g = 0 is the tracing floor.
+    that g (so g = +-0.35 are phases the pool-trained field never saw).  The error between two
+    independent reference traces at g = 0 is the tracing floor.
+
+    Network settings: the configuration against the paper's encoding and network (16 levels x 8
+    features, growth 2, 5 hidden layers, batches of 2^16, relative or plain L2), trained on a
+    5-phase trace and judged at g = 0.4 and 0.2, with training time and 640x480 frame time.
 
     Noise: the Algorithm 2 renderer with the field and the path tracer (at most 16 collisions)
     at 1, 4 and 8 spp; the noise of each is the RMS difference of two frames with different
@@ -852,10 +897,15 @@ def studies(args):
     photons = 1 << args.st_photons
     st = ctx.trace_photon_cache(photons, G3, cache_res=128, seed=21, max_collisions=8,
                                 rr_start=3)
-    ctx.field_select(0)
-    ctx.field_init(FieldConfig(), seed=21)
-    hist = ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, seed=21))
-    log(f"[st] trained on G = {G3}: {st['n_records']} records, loss {np.mean(hist[-20:]):.4g}")
+    # slot 0: g drawn from the pool G (Section 3.5.1); slot 6: g uniform over [-0.75, 0.75]
+    # against the trace's cache linear in g between its bins
+    for slot, gs in ((0, "pool"), (6, "uniform")):
+        ctx.field_select(slot)
+        ctx.field_init(FieldConfig(), seed=21)
+        hist = ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, seed=21,
+                                           g_sampling=gs))
+        log(f"[st] trained on G = {G3} ({gs} g): {st['n_records']} records, loss "
+            f"{np.mean(hist[-20:]):.4g}")
 
     def rc(g, indirect, spp=1, seed=3):
         return RenderConfig(spp=spp, step_voxels=0.5, max_steps=1024, t_min=1e-3, field_stride=4,
@@ -867,10 +917,13 @@ def studies(args):
         torch.cuda.synchronize()
         return out.cpu().numpy().astype(np.float64)
 
-    def li_field(g):
-        return frame(rc(g, INDIRECT_FIELD)) - frame(rc(g, INDIRECT_NONE))
+    def li_field(g, slot=0):
+        cfg = rc(g, INDIRECT_FIELD)
+        cfg.field_slot = slot
+        return frame(cfg) - frame(rc(g, INDIRECT_NONE))
 
     field_li = {g: li_field(g) for g in (-0.75, -0.35, 0.0, 0.35, 0.75)}
+    field_li_u = {g: li_field(g, 6) for g in (-0.75, -0.35, 0.0, 0.35, 0.75)}
     # the training trace's own cache, linear in g between its bins: the estimate without network
     cache_li = {g: frame(rc(g, INDIRECT_CACHE)) - frame(rc(g, INDIRECT_NONE))
                 for g in (-0.75, -0.35, 0.0, 0.35, 0.75)}
@@ -883,14 +936,18 @@ def studies(args):
     phase = []
     for i, g in enumerate((-0.75, -0.35, 0.0, 0.35, 0.75)):
         ref = li_reference(g, 100 + i)
-        f, c = field_li[g], cache_li[g]
+        f, fu, c = field_li[g], field_li_u[g], cache_li[g]
         rel = lambda a: float(np.sqrt(np.mean((a - ref) ** 2)) / ref.mean())
         phase.append({"g": g, "in_training_set": g in G3, "rel_rmse": rel(f), "ssim": ssim(f, ref),
+                      "uniform_g_rel_rmse": rel(fu), "uniform_g_ssim": ssim(fu, ref),
                       "cache_interp_rel_rmse": rel(c), "cache_interp_ssim": ssim(c, ref),
-                      "li_mean": float(ref.mean()), "field_li_mean": float(f.mean())})
+                      "li_mean": float(ref.mean()), "field_li_mean": float(f.mean()),
+                      "uniform_g_li_mean": float(fu.mean())})
         log(f"[st] g={g:+.2f} ({'trained' if g in G3 else 'unseen '}): L_i rel-RMSE "
             f"{phase[-1]['rel_rmse']:.4f}, SSIM {phase[-1]['ssim']:.4f} (field mean "
-            f"{f.mean():.4g} vs {ref.mean():.4g}); 3-bin cache in g: rel-RMSE {rel(c):.4f}, "
+            f"{f.mean():.4g} vs {ref.mean():.4g}); uniform g: rel-RMSE "
+            f"{phase[-1]['uniform_g_rel_rmse']:.4f}, SSIM {phase[-1]['uniform_g_ssim']:.4f} "
+            f"(mean {fu.mean():.4g}); 3-bin cache in g: rel-RMSE {rel(c):.4f}, "
             f"SSIM {phase[-1]['cache_interp_ssim']:.4f}")
     a, b = li_reference(0.0, 300), li_reference(0.0, 301)
     floor = {"rel_rmse": float(np.sqrt(np.mean((a - b) ** 2)) / b.mean()), "ssim": ssim(a, b)}
@@ -916,20 +973,25 @@ def studies(args):
         npt = float(np.sqrt(np.mean((pt(spp, 1) - pt(spp, 2)) ** 2) / 2) / ref.mean())
         noise.append({"spp": spp, "field_first_interaction": nf, "path_tracer": npt})
         log(f"[st] {spp} spp: relative noise field {nf:.4f}, path tracer {npt:.4f}")
-    # the configuration against the paper's network settings (but for its 8 features per level):
-    # 5 hidden layers, level growth 2 (12 levels, so that the finest stays within the 2^16 grid
-    # coordinates of the encoding), batches of 2^16, relative L2; trained on one 5-phase trace
-    # and judged on L_i against single-phase reference traces
+    # the configuration against the paper's network settings (Sections 3.4 and 3.5.1: 16 levels
+    # x 8 features, growth 2, 5 hidden layers, batches of 2^16, relative L2), with g from the
+    # pool and uniform in [-0.8, 0.8]; trained on one 5-phase trace and judged on L_i against
+    # single-phase reference traces
     st5 = ctx.trace_photon_cache(photons, wl.C1_G_BINS, cache_res=128, seed=31, max_collisions=8,
                                  rr_start=3)
+    paper = FieldConfig(hidden_layers=5, growth=2.0, levels=16, feats_per_level=8)
     variants = {
         "configuration": (FieldConfig(), TrainConfig(steps=args.train_steps, log2_batch=18,
                                                      seed=31)),
-        "paper_network_rel_l2": (FieldConfig(hidden_layers=5, growth=2.0, levels=12),
-                                 TrainConfig(steps=args.train_steps, log2_batch=16, seed=31,
-                                             loss="rel")),
-        "paper_network_l2": (FieldConfig(hidden_layers=5, growth=2.0, levels=12),
-                             TrainConfig(steps=args.train_steps, log2_batch=16, seed=31)),
+        "configuration_uniform_g": (FieldConfig(),
+                                    TrainConfig(steps=args.train_steps, log2_batch=18, seed=31,
+                                                g_sampling="uniform")),
+        "paper_network_rel_l2": (paper, TrainConfig(steps=args.train_steps, log2_batch=16,
+                                                    seed=31, loss="rel")),
+        "paper_network_l2": (paper, TrainConfig(steps=args.train_steps, log2_batch=16, seed=31)),
+        "paper_network_rel_l2_uniform_g": (paper, TrainConfig(steps=args.train_steps,
+                                                              log2_batch=16, seed=31, loss="rel",
+                                                              g_sampling="uniform")),
     }
     ab = {}
     for slot, (name, (fc, tc)) in enumerate(variants.items()):
@@ -939,9 +1001,20 @@ def studies(args):
         ts = time.perf_counter()
         hist = ctx.train_field(tc)
         torch.cuda.synchronize()
-        ab[name] = {"hidden_layers": fc.hidden_layers, "growth": fc.growth,
-                    "batch": 1 << tc.log2_batch, "loss": tc.loss,
-                    "train_s": round(time.perf_counter() - ts, 3),
+        train_s = time.perf_counter() - ts
+        cfg = rc(0.4, INDIRECT_FIELD)
+        cfg.field_slot = 1 + slot
+        frame(cfg)
+        tf0 = time.perf_counter()
+        for _ in range(5):
+            ctx.render_frame(cam, cfg)
+        torch.cuda.synchronize()
+        ab[name] = {"levels": fc.levels, "feats_per_level": fc.feats_per_level,
+                    "hidden_layers": fc.hidden_layers, "growth": fc.growth,
+                    "n_params": ctx.field_num_params(),
+                    "batch": 1 << tc.log2_batch, "loss": tc.loss, "g_sampling": tc.g_sampling,
+                    "train_s": round(train_s, 3),
+                    "frame_ms": round((time.perf_counter() - tf0) * 200.0, 3),
                     "final_loss": float(np.mean(hist[-20:])), "per_g": {}}
     for i, g in enumerate((0.4, 0.2)):
         ref = li_reference(g, 400 + i)

@@ -158,9 +158,12 @@ pfn_status pfn_photon_map_estimate(pfn_context *ctx, const float *dev_xyz, const
 /* ------------------------------------------------------------------ 2. photon field */
 typedef struct {
   int levels;          /* grid levels (1..16) */
-  int feats_per_level; /* 2 */
-  int base_res;        /* coarsest grid resolution */
-  float growth;        /* per-level resolution factor; N_l = floor(base_res * growth^l) */
+  int feats_per_level; /* 2 or 8 (Section 3.4: the paper's encoding stores 8); renders of a field
+                          with 8 run in the wavefront form only (the fused kernel returns
+                          PFN_ERR_UNSUPPORTED for them) */
+  int base_res;        /* coarsest grid resolution (2..4096) */
+  float growth;        /* per-level resolution factor in [1, 4]; N_l = floor(base_res * growth^l),
+                          below 2^24 cells per axis (16 levels at growth 2 from 16 reach 2^19) */
   int log2_table;      /* hashed-level table size 2^log2_table (dense levels are exact) */
   int hidden_layers;   /* ReLU hidden layers (1..7) of width 64, no biases, linear output */
   int width;           /* 64 */
@@ -353,7 +356,8 @@ pfn_status pfn_set_launch_mode(pfn_context *ctx, int persistent_per_cu, int use_
  *   PFN_STRATEGY_AUTO (default): the wavefront form, unless graph replay was asked for (then
  *     the fused kernel).
  * Device buffers of the wavefront form (two sets of about 2.9 KB per ray of a round with 16-bit
- * features, 5 KB with FP32, at most 2^21 rays per round, plus 24 B per ray sample of the frame)
+ * features, 5 KB with FP32, at most 2^21 rays per round, or 2^19 for fields of 8 features per
+ * level, whose features take four times the room, plus 24 B per ray sample of the frame)
  * are kept in the context and grown on demand.  Both wavefront variants give bit-identical
  * images. */
 typedef enum {

@@ -397,7 +397,7 @@ extern "C" pfn_status pfn_field_select(pfn_context *ctx, int slot) {
 
 static pfn_status field_layout(pfn_context *ctx, const pfn_field_desc *d, FieldSlot &f) {
   ARG(d->levels >= 1 && d->levels <= PFN_MAX_LEVELS, "levels in [1, 16]");
-  ARG(d->feats_per_level == 2, "feats_per_level must be 2");
+  ARG(d->feats_per_level == 2 || d->feats_per_level == 8, "feats_per_level must be 2 or 8");
   ARG(d->base_res >= 2 && d->base_res <= 4096, "base_res in [2, 4096]");
   ARG(std::isfinite(d->growth) && d->growth >= 1.0f && d->growth <= 4.0f, "growth in [1, 4]");
   ARG(d->log2_table >= 4 && d->log2_table <= 24, "log2_table in [4, 24]");
@@ -411,8 +411,9 @@ static pfn_status field_layout(pfn_context *ctx, const pfn_field_desc *d, FieldS
   f.pos = GridLevels{};
   f.dir = GridLevels{};
   for (int l = 0; l < d->levels; ++l) {
+    // FP32 positions carry 24 bits: a finer level could not resolve its cells
+    ARG(r < 16777216.0, "level resolution above 2^24");
     int res = (int)std::floor(r);
-    ARG(res < 65535, "level resolution too large");
     size_t d3 = (size_t)(res + 1) * (res + 1) * (res + 1), d2 = (size_t)(res + 1) * (res + 1);
     f.pos.res[l] = res;
     f.pos.off[l] = (uint32_t)off;
@@ -426,9 +427,10 @@ static pfn_status field_layout(pfn_context *ctx, const pfn_field_desc *d, FieldS
   }
   f.pos_entries = off;
   f.dir_entries = offd;
-  f.mlp_off = 2 * (off + offd);
+  const int F = d->feats_per_level;
+  f.mlp_off = (size_t)F * (off + offd);
   size_t w = f.mlp_off;
-  int n_in = 4 * d->levels + 1;
+  int n_in = 2 * F * d->levels + 1;
   for (int m = 0; m <= d->hidden_layers; ++m) {
     f.w_off[m] = w;
     int rows = (m == d->hidden_layers) ? 3 : d->width;
@@ -454,11 +456,13 @@ extern "C" pfn_status pfn_field_init(pfn_context *ctx, const pfn_field_desc *des
   PFN_HIP(ctx, dev_alloc((void **)&f.adam_m, n * 4));
   PFN_HIP(ctx, dev_alloc((void **)&f.adam_v, n * 4));
   PFN_HIP(ctx, dev_alloc((void **)&f.grad, n * 4));
-  size_t entries = f.pos_entries + f.dir_entries;
+  // 16-bit copies: one 32-bit word per pair of features
+  size_t entries = (f.pos_entries + f.dir_entries) * (size_t)(desc->feats_per_level / 2);
   for (int p = 1; p <= 2; ++p) PFN_HIP(ctx, dev_alloc((void **)&f.lp_table[p], entries * 4));
   for (int p = 0; p <= 2; ++p)
     PFN_HIP(ctx, dev_alloc(&f.mlp_packed[p],
-                           (size_t)mlp_packed_elems(p, desc->hidden_layers) * (p ? 2 : 4)));
+                           (size_t)mlp_packed_elems(p, desc->hidden_layers,
+                                                    desc->feats_per_level / 2) * (p ? 2 : 4)));
   PFN_HIP(ctx, hipMemsetAsync(f.adam_m, 0, n * 4, ctx->stream));
   PFN_HIP(ctx, hipMemsetAsync(f.adam_v, 0, n * 4, ctx->stream));
   PFN_HIP(ctx, hipMemsetAsync(f.grad, 0, n * 4, ctx->stream));
@@ -683,14 +687,19 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
       if (st) return st;
       fd[s] = make_field_dev(f, prec);
       mp[s] = f.mlp_packed[prec];
-      mlp_bytes = mlp_packed_elems(prec, f.desc.hidden_layers) * (prec == P_F32 ? 4 : 2);
+      mlp_bytes = mlp_packed_elems(prec, f.desc.hidden_layers, f.desc.feats_per_level / 2) *
+                  (prec == P_F32 ? 4 : 2);
     }
     for (int i = 0; i < n_jobs; ++i) {
-      int hs = ctx->fields[jobs[i].params.field_slot].desc.hidden_layers;
-      if (hs != ctx->fields[jobs[0].params.field_slot].desc.hidden_layers)
-        return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "batched fields must share hidden_layers");
+      const pfn_field_desc &di = ctx->fields[jobs[i].params.field_slot].desc;
+      const pfn_field_desc &d0 = ctx->fields[jobs[0].params.field_slot].desc;
+      if (di.hidden_layers != d0.hidden_layers || di.feats_per_level != d0.feats_per_level)
+        return pfn_fail(ctx, PFN_ERR_UNSUPPORTED,
+                        "batched fields must share hidden_layers and feats_per_level");
     }
   }
+  const bool wide_field = p0.indirect == PFN_INDIRECT_FIELD &&
+                          ctx->fields[p0.field_slot].desc.feats_per_level != 2;
   // upload job table and field descriptors
   size_t jb = sizeof(MarchJob) * n_jobs;
   if (ctx->jobs_cap < (size_t)n_jobs) {
@@ -753,10 +762,14 @@ pfn_status run_march(pfn_context *ctx, const pfn_render_job *jobs, int n_jobs, c
   }
   // the wavefront form when the caller (or the autotuner) chose it, or by default where no
   // graph replay was asked for; graph replay applies to the fused kernel only
+  // (a field with 8 features per level is evaluated by the wavefront kernels only)
   const bool wavefront =
       p0.indirect == PFN_INDIRECT_FIELD &&
       (ctx->strategy == PFN_STRATEGY_WAVEFRONT || ctx->strategy == PFN_STRATEGY_WAVEFRONT_SERIAL ||
-       (ctx->strategy == PFN_STRATEGY_AUTO && !ctx->use_graph));
+       (ctx->strategy == PFN_STRATEGY_AUTO && (!ctx->use_graph || wide_field)));
+  if (wide_field && !wavefront && !first_interaction)
+    return pfn_fail(ctx, PFN_ERR_UNSUPPORTED,
+                    "the fused kernel evaluates fields of 2 features per level only");
   if (first_interaction) {
     pfn_status st = run_first_interaction(ctx, a, mj[0], p0.indirect, prec, p0.field_slot,
                                           fd[p0.field_slot]);
@@ -1038,14 +1051,17 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
   put(&jobs[0].params.field_precision, sizeof(int));
   put(&ctx->vol_grid, sizeof(BrickGrid));
   put(&ctx->vol_dtype, sizeof(int));
-  // forms to time: the one the caller fixed, else the fused kernel and (field-lit batches) the
-  // overlapped wavefront rounds
+  const bool field_lit = jobs[0].params.indirect == PFN_INDIRECT_FIELD;
+  const int feats = field_lit ? ctx->fields[jobs[0].params.field_slot].desc.feats_per_level : 0;
+  put(&feats, sizeof(int));
+  // forms to time: the one the caller fixed, else the fused kernel (fields of 2 features per
+  // level) and (field-lit batches) the overlapped wavefront rounds
   const int saved_strategy = ctx->strategy;
   std::vector<int> forms;
   if (saved_strategy != PFN_STRATEGY_AUTO) forms.push_back(saved_strategy);
   else {
-    forms.push_back(PFN_STRATEGY_FUSED);
-    if (jobs[0].params.indirect == PFN_INDIRECT_FIELD) forms.push_back(PFN_STRATEGY_WAVEFRONT);
+    if (feats != 8) forms.push_back(PFN_STRATEGY_FUSED);
+    if (field_lit) forms.push_back(PFN_STRATEGY_WAVEFRONT);
   }
   if (jobs[0].params.indirect != PFN_INDIRECT_FIELD) forms.assign(1, PFN_STRATEGY_FUSED);
   const bool saved_graph = ctx->use_graph, saved_timing = ctx->timing;

@@ -40,7 +40,7 @@ hipError_t launch_field_init(pfn_context *ctx, FieldSlot &f, uint64_t seed) {
   for (int m = 0; m < nm; ++m) {
     a.w_off[m] = f.w_off[m];
     a.rows[m] = (m == nm - 1) ? 3 : f.desc.width;
-    a.cols[m] = (m == 0) ? (4 * f.desc.levels + 1) : f.desc.width;
+    a.cols[m] = (m == 0) ? (2 * f.desc.feats_per_level * f.desc.levels + 1) : f.desc.width;
   }
   a.w_off[nm] = f.n_params;
   a.n_mats = nm;
@@ -52,6 +52,8 @@ hipError_t launch_field_init(pfn_context *ctx, FieldSlot &f, uint64_t seed) {
 }
 
 // ------------------------------------------------------------------ low-precision copies
+// One 32-bit word (two 16-bit features) per pair of consecutive FP32 features; an entry of 2 fg
+// features is fg words.
 template <int P>
 __global__ void pack_grid_kernel(const float2 *__restrict__ master, uint32_t *__restrict__ lp,
                                  size_t entries) {
@@ -71,15 +73,19 @@ __global__ void pack_grid_kernel(const float2 *__restrict__ master, uint32_t *__
 struct PackArgs {
   const float *w[PFN_MAX_HIDDEN + 1];  // weight matrices (row-major out x in)
   int hidden, levels, n_in;
+  int fg;                              // feature groups (features per level / 2)
 };
 
-// Column of W_0 that feeds lane group q, slot i of input chunk c (-1: zero padding).
+// Column of W_0 that feeds lane group q, slot i of the chunk of feature group grp of kind
+// (0 position, 1 direction): feature 2 grp + (i & 1) of level 4q + i / 2 (-1: zero padding).
+__device__ __forceinline__ int in_col_g(const PackArgs &a, int kind, int grp, int q, int i) {
+  const int lv = 4 * q + (i >> 1), f = i & 1, F = 2 * a.fg;
+  if (lv >= a.levels) return -1;
+  return kind * F * a.levels + F * lv + 2 * grp + f;
+}
+// 16-bit input chunk c of a row tile: fg position groups, fg direction groups, then g.
 __device__ __forceinline__ int in_col(const PackArgs &a, int c, int q, int i) {
-  if (c == 0 || c == 1) {
-    int lv = 4 * q + (i >> 1), f = i & 1;
-    if (lv >= a.levels) return -1;
-    return c * 2 * a.levels + 2 * lv + f;
-  }
+  if (c < 2 * a.fg) return in_col_g(a, c / a.fg, c % a.fg, q, i);
   return (q == 0 && i == 0) ? a.n_in - 1 : -1;
 }
 // Neuron held by lane group q, slot i of hidden chunk c (two accumulator tiles per chunk).
@@ -94,12 +100,13 @@ __global__ void pack_mlp16_kernel(PackArgs a, void *out_v, int total) {
   int i = idx & 7, l = (idx >> 3) & 63, blk = idx >> 9;  // blk: (matrix tile, chunk) pair
   int row = l & 15, q = l >> 4;
   float v = 0.0f;
-  if (blk < 12) {
-    int mt = blk / 3, c = blk % 3;
+  const int C = 2 * a.fg + 1;
+  if (blk < 4 * C) {
+    int mt = blk / C, c = blk % C;
     int col = in_col(a, c, q, i);
     if (col >= 0) v = a.w[0][(16 * mt + row) * a.n_in + col];
   } else {
-    int rb = blk - 12;
+    int rb = blk - 4 * C;
     int h = 1 + rb / 8;
     if (h < a.hidden) {
       int mt = (rb % 8) / 2, c = rb % 2;
@@ -122,18 +129,20 @@ __global__ void pack_mlp32_kernel(PackArgs a, float *out, int total) {
   int l = idx & 63, blk = idx >> 6;
   int row = l & 15, q = l >> 4;
   float v = 0.0f;
-  if (blk < 4 * 17) {
-    int mt = blk / 17, c = blk % 17;
+  const int C = 16 * a.fg + 1;
+  if (blk < 4 * C) {
+    int mt = blk / C, c = blk % C;
     int col = -1;
-    if (c < 16) {
-      int cc = c >> 3, i = c & 7;  // position (cc = 0) or direction (cc = 1) feature 8q + i
-      col = in_col(a, cc, q, i);
+    if (c < 16 * a.fg) {
+      // 8 chunks per feature group and kind: chunk i carries slot i (feature 8q + i of the group)
+      int kind = c / (8 * a.fg), grp = (c % (8 * a.fg)) >> 3, i = c & 7;
+      col = in_col_g(a, kind, grp, q, i);
     } else if (q == 0) {
       col = a.n_in - 1;
     }
     if (col >= 0) v = a.w[0][(16 * mt + row) * a.n_in + col];
   } else {
-    int rb = blk - 4 * 17;
+    int rb = blk - 4 * C;
     int h = 1 + rb / 64;
     if (h < a.hidden) {
       int mt = (rb % 64) / 16, tr = rb % 16;
@@ -154,8 +163,9 @@ hipError_t launch_field_pack_mlp(pfn_context *ctx, FieldSlot &f, int prec) {
   for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
   a.hidden = f.desc.hidden_layers;
   a.levels = f.desc.levels;
-  a.n_in = 4 * f.desc.levels + 1;
-  int total = mlp_packed_elems(prec, a.hidden);
+  a.fg = f.desc.feats_per_level / 2;
+  a.n_in = 2 * f.desc.feats_per_level * f.desc.levels + 1;
+  int total = mlp_packed_elems(prec, a.hidden, a.fg);
   unsigned blocks = (unsigned)((total + 255) / 256);
   if (prec == P_F32)
     hipLaunchKernelGGL(pack_mlp32_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a,
@@ -174,14 +184,16 @@ hipError_t launch_field_pack(pfn_context *ctx, FieldSlot &f, int prec) {
   for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
   a.hidden = f.desc.hidden_layers;
   a.levels = f.desc.levels;
-  a.n_in = 4 * f.desc.levels + 1;
-  int total = mlp_packed_elems(prec, a.hidden);
+  a.fg = f.desc.feats_per_level / 2;
+  a.n_in = 2 * f.desc.feats_per_level * f.desc.levels + 1;
+  int total = mlp_packed_elems(prec, a.hidden, a.fg);
   if (prec == P_F32) {
     hipLaunchKernelGGL(pack_mlp32_kernel, dim3((total + 255) / 256), dim3(256), 0, ctx->stream, a,
                        (float *)f.mlp_packed[prec], total);
     return hipGetLastError();
   }
-  size_t entries = f.pos_entries + f.dir_entries;
+  // feature pairs of both grids (one 32-bit word each)
+  size_t entries = (f.pos_entries + f.dir_entries) * (size_t)(f.desc.feats_per_level / 2);
   unsigned gb = (unsigned)((entries + 255) / 256);
   if (prec == P_F16) {
     hipLaunchKernelGGL(pack_grid_kernel<P_F16>, dim3(gb), dim3(256), 0, ctx->stream,
@@ -201,27 +213,31 @@ FieldDev make_field_dev(const FieldSlot &f, int prec) {
   FieldDev F{};
   F.pos = f.pos;
   F.dir = f.dir;
+  const int fg = f.desc.feats_per_level / 2;
   if (prec == P_F32) {
     F.pos_table = f.master;
-    F.dir_table = f.master + 2 * f.pos_entries;
+    F.dir_table = f.master + 2 * fg * f.pos_entries;
   } else {
     F.pos_table = f.lp_table[prec];
-    F.dir_table = f.lp_table[prec] + f.pos_entries;
+    F.dir_table = f.lp_table[prec] + fg * f.pos_entries;
   }
   F.hash_mask = (uint32_t)((1ull << f.desc.log2_table) - 1);
-  // wide loads of entry pairs need each table to start at a multiple of two entries
+  // wide loads of entry pairs need each table to start at a multiple of two entries (two
+  // features per entry only; 8-feature entries are 16- or 32-byte loads of their own)
   const size_t pair_bytes = prec == P_F32 ? 16 : 8;
-  F.pair_ok = (((uintptr_t)F.pos_table % pair_bytes) == 0 ? 1u : 0u) |
-              (((uintptr_t)F.dir_table % pair_bytes) == 0 ? 2u : 0u);
+  F.pair_ok = fg != 1 ? 0u
+                      : ((((uintptr_t)F.pos_table % pair_bytes) == 0 ? 1u : 0u) |
+                         (((uintptr_t)F.dir_table % pair_bytes) == 0 ? 2u : 0u));
   F.levels = f.desc.levels;
   F.hidden = f.desc.hidden_layers;
+  F.fg = fg;
   F.psi = f.desc.psi;
   F.kappa = (float)f.kappa;
   return F;
 }
 
 // ------------------------------------------------------------------ batched query
-template <int P>
+template <int P, int FG>
 __global__ __launch_bounds__(QUERY_THREADS) void field_query_kernel(
     FieldDev F, const void *__restrict__ mlp, int mlp_bytes, const float *__restrict__ xyz,
     const float *__restrict__ dir, const float *__restrict__ g, int64_t n, float *__restrict__ lp,
@@ -246,7 +262,7 @@ __global__ __launch_bounds__(QUERY_THREADS) void field_query_kernel(
       }
       float u0, u1;
       dir_coords(w, u0, u1);
-      f32x4 out = field_tile16<P>(F, lds_w, x, u0, u1, gg, valid);
+      f32x4 out = field_tile16_g<P, FG>(F, lds_w, x, u0, u1, gg, valid);
       if (lane < 16 && valid) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -261,17 +277,31 @@ __global__ __launch_bounds__(QUERY_THREADS) void field_query_kernel(
 hipError_t launch_field_query(pfn_context *ctx, const FieldSlot &f, int prec, const float *xyz,
                               const float *dir, const float *g, int64_t n, float *lp, float *rgb) {
   FieldDev F = make_field_dev(f, prec);
-  int bytes = mlp_packed_elems(prec, f.desc.hidden_layers) * (prec == P_F32 ? 4 : 2);
+  const int fg = f.desc.feats_per_level / 2;
+  int bytes = mlp_packed_elems(prec, f.desc.hidden_layers, fg) * (prec == P_F32 ? 4 : 2);
   int64_t blocks = (n + QUERY_THREADS - 1) / QUERY_THREADS;
   if (blocks < 1) blocks = 1;
-  if (prec == P_F32)
-    hipLaunchKernelGGL(field_query_kernel<P_F32>, dim3((unsigned)blocks), dim3(QUERY_THREADS),
-                       bytes, ctx->stream, F, f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-  else if (prec == P_BF16)
-    hipLaunchKernelGGL(field_query_kernel<P_BF16>, dim3((unsigned)blocks), dim3(QUERY_THREADS),
-                       bytes, ctx->stream, F, f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-  else
-    hipLaunchKernelGGL(field_query_kernel<P_F16>, dim3((unsigned)blocks), dim3(QUERY_THREADS),
-                       bytes, ctx->stream, F, f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+  const dim3 gr((unsigned)blocks), bl(QUERY_THREADS);
+  if (fg == 1) {
+    if (prec == P_F32)
+      hipLaunchKernelGGL((field_query_kernel<P_F32, 1>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+    else if (prec == P_BF16)
+      hipLaunchKernelGGL((field_query_kernel<P_BF16, 1>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+    else
+      hipLaunchKernelGGL((field_query_kernel<P_F16, 1>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+  } else {
+    if (prec == P_F32)
+      hipLaunchKernelGGL((field_query_kernel<P_F32, 4>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+    else if (prec == P_BF16)
+      hipLaunchKernelGGL((field_query_kernel<P_BF16, 4>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+    else
+      hipLaunchKernelGGL((field_query_kernel<P_F16, 4>), gr, bl, bytes, ctx->stream, F,
+                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+  }
   return hipGetLastError();
 }

@@ -253,8 +253,10 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
   job.spp = groups;
   job.inv_spp = 1.0f / (float)spp;
   job.ray_begin = 0;
-  const size_t entries = (size_t)std::min<int64_t>(rays, WF_MAX_ENTRIES);
-  const size_t fbytes = prec == P_F32 ? 8 : 4;
+  // chunks of fewer rays for wider features, so that the feature buffers keep their size
+  const int fg = indirect == PFN_INDIRECT_FIELD ? fd_host.fg : 1;
+  const size_t entries = (size_t)std::min<int64_t>(rays, WF_MAX_ENTRIES / fg);
+  const size_t fbytes = (prec == P_F32 ? 8 : 4) * (size_t)fg;
   PFN_HIP(ctx, wf_reserve(w, entries, (size_t)rays, fbytes));
   if (w.pix_cap < 2) {
     if (w.pix_begin) (void)hipFree(w.pix_begin);
@@ -273,7 +275,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
   int fb_max = 1;
   if (indirect == PFN_INDIRECT_FIELD) {
     lgroups = wf_level_groups(ctx, slot, fd_host, fbytes);
-    fb_max = wf_field_blocks(prec, m.mlp_bytes);
+    fb_max = wf_field_blocks(prec, m.mlp_bytes, fg);
   }
   hipStream_t sa = ctx->stream, sb = w.side;
   WfRound &b = w.rb[0], &st = w.rb[1];
@@ -368,6 +370,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
       f.acc_i = w.acc_i;
       f.n_slots = e.n_slots;
       f.n_entries = a.n_entries;
+      f.fg = fg;
       f.n_cont = 0;
       f.in_ci = nullptr;
       f.out_ci = nullptr;

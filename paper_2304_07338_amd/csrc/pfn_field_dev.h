@@ -32,19 +32,24 @@ struct GridLevels {
 
 struct FieldDev {
   GridLevels pos, dir;
-  const void *pos_table;  // f32: float2 per entry; f16/bf16: 2 packed 16-bit features per entry
+  // An entry holds 2 * fg features: f32 tables fg float2 per entry, f16/bf16 tables fg 32-bit
+  // words (2 packed 16-bit features each) per entry.
+  const void *pos_table;
   const void *dir_table;
   uint32_t hash_mask;     // 2^log2_table - 1
   uint32_t pair_ok;       // bit 0 / 1: the position / direction table starts on a pair of entries
   int levels;
   int hidden;             // hidden layers
+  int fg;                 // feature groups: features per level / 2 (1 or 4)
   float psi, kappa;
 };
 
-// Sizes (in elements) of the packed MLP image in LDS order.
-__host__ __device__ constexpr int mlp_packed_elems(int prec, int hidden) {
-  return prec == P_F32 ? (4 * 17 * 64 + (hidden - 1) * 4 * 16 * 64 + 16 * 64)
-                       : (4 * 3 * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 2 * 64 * 8);
+// Sizes (in elements) of the packed MLP image in LDS order.  The input layer has, per 16-row
+// tile, fg position chunks, fg direction chunks and one g chunk (16-bit: K = 32 per chunk; FP32:
+// 8 K = 4 chunks per feature group and kind, and one for g).
+__host__ __device__ constexpr int mlp_packed_elems(int prec, int hidden, int fg = 1) {
+  return prec == P_F32 ? (4 * (16 * fg + 1) * 64 + (hidden - 1) * 4 * 16 * 64 + 16 * 64)
+                       : (4 * (2 * fg + 1) * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 2 * 64 * 8);
 }
 
 // ------------------------------------------------------------------ encoding
@@ -170,6 +175,78 @@ __device__ __forceinline__ float2 encode_dir_level(const FieldDev &F, int lv, fl
   return acc;
 }
 
+// ---------------- 8 features per level (4 feature groups): one entry is 16 bytes at 16 bits
+// (one load per corner) or 32 bytes in FP32 (two loads).
+template <int P>
+__device__ __forceinline__ void load_feat8(const void *table, uint32_t e, float v[8]) {
+  if constexpr (P == P_F32) {
+    const float4 a = reinterpret_cast<const float4 *>(table)[2 * (size_t)e];
+    const float4 b = reinterpret_cast<const float4 *>(table)[2 * (size_t)e + 1];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+    const uint4 w = reinterpret_cast<const uint4 *>(table)[e];
+    const float2 f0 = unpack_feat<P>(w.x), f1 = unpack_feat<P>(w.y), f2 = unpack_feat<P>(w.z),
+                 f3v = unpack_feat<P>(w.w);
+    v[0] = f0.x; v[1] = f0.y; v[2] = f1.x; v[3] = f1.y;
+    v[4] = f2.x; v[5] = f2.y; v[6] = f3v.x; v[7] = f3v.y;
+  }
+}
+
+// Level `lv` of the position grid at x, 8 features.
+template <int P>
+__device__ __forceinline__ void encode_pos_level8(const FieldDev &F, int lv, f3 x, float acc[8]) {
+  const int N = F.pos.res[lv];
+  const uint32_t off = F.pos.off[lv];
+  const bool dense = (F.pos.dense_mask >> lv) & 1u;
+  int cx, cy, cz;
+  float fx, fy, fz;
+  level_cell(x.x, N, cx, fx);
+  level_cell(x.y, N, cy, fy);
+  level_cell(x.z, N, cz, fz);
+  const uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+#pragma unroll
+  for (int f = 0; f < 8; ++f) acc[f] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1)),
+                   vz = (uint32_t)(cz + ((k >> 2) & 1));
+    const uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+    const float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy) *
+                    (((k >> 2) & 1) ? fz : 1.0f - fz);
+    float v[8];
+    load_feat8<P>(F.pos_table, off + idx, v);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) acc[f] = fmaf(w, v[f], acc[f]);
+  }
+}
+
+// Level `lv` of the direction grid at (u0, u1), 8 features.
+template <int P>
+__device__ __forceinline__ void encode_dir_level8(const FieldDev &F, int lv, float u0, float u1,
+                                                  float acc[8]) {
+  const int N = F.dir.res[lv];
+  const uint32_t off = F.dir.off[lv];
+  const bool dense = (F.dir.dense_mask >> lv) & 1u;
+  int cx, cy;
+  float fx, fy;
+  level_cell(u0, N, cx, fx);
+  level_cell(u1, N, cy, fy);
+  const uint32_t s1 = (uint32_t)(N + 1);
+#pragma unroll
+  for (int f = 0; f < 8; ++f) acc[f] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t vx = (uint32_t)(cx + (k & 1)), vy = (uint32_t)(cy + ((k >> 1) & 1));
+    const uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+    const float w = ((k & 1) ? fx : 1.0f - fx) * (((k >> 1) & 1) ? fy : 1.0f - fy);
+    float v[8];
+    load_feat8<P>(F.dir_table, off + idx, v);
+#pragma unroll
+    for (int f = 0; f < 8; ++f) acc[f] = fmaf(w, v[f], acc[f]);
+  }
+}
+
 // Normalised spherical coordinates (theta/pi, (phi+pi)/(2pi)) of a unit direction, in FP32.
 // The cell and fraction on a direction level then come from level_cell's single-rounding
 // split.  An error of a few ulps in the coordinate (acosf, atan2f and the scaling each round
@@ -204,6 +281,37 @@ __device__ __forceinline__ void encode_lane(const FieldDev &F, int q, f3 x, floa
     pos[2 * j + 1] = a.y;
     dir[2 * j] = b.x;
     dir[2 * j + 1] = b.y;
+  }
+}
+
+// The same for FG feature groups: pos[g][2j + f] / dir[g][2j + f] = feature 2g + f of
+// level 4q + j.  FG = 1 is encode_lane.
+template <int P, int FG>
+__device__ __forceinline__ void encode_lane_g(const FieldDev &F, int q, f3 x, float u0, float u1,
+                                              bool valid, float (&pos)[FG][8],
+                                              float (&dir)[FG][8]) {
+  if constexpr (FG == 1) {
+    encode_lane<P>(F, q, x, u0, u1, valid, pos[0], dir[0]);
+  } else {
+    static_assert(FG == 4, "feature groups: 1 or 4");
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int lv = 4 * q + j;
+      float a[8], b[8];
+#pragma unroll
+      for (int f = 0; f < 8; ++f) a[f] = b[f] = 0.0f;
+      if (valid && lv < F.levels) {
+        encode_pos_level8<P>(F, lv, x, a);
+        encode_dir_level8<P>(F, lv, u0, u1, b);
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        pos[g][2 * j] = a[2 * g];
+        pos[g][2 * j + 1] = a[2 * g + 1];
+        dir[g][2 * j] = b[2 * g];
+        dir[g][2 * j + 1] = b[2 * g + 1];
+      }
+    }
   }
 }
 
@@ -264,16 +372,14 @@ __device__ __forceinline__ void mlp_input16(const typename Mma<P>::vec *__restri
 
 // Second part: the position product, the hidden layers and the output layer.  Returns the
 // output tile: lanes 0..15 hold (L'_r, L'_g, L'_b, 0) of query l.
+// Hidden layers 2..H and the output layer, from the first hidden layer's activations acc; wl
+// points at the image of W_1.
 template <int P>
-__device__ __forceinline__ f32x4 mlp_rest16(const typename Mma<P>::vec *__restrict__ w, int hidden,
-                                            typename Mma<P>::vec b0, const f32x4 pre[4]) {
+__device__ __forceinline__ f32x4 mlp_tail16(const typename Mma<P>::vec *__restrict__ wl,
+                                            int hidden, f32x4 acc[4]) {
   typedef Mma<P> M;
   typedef typename M::vec vec;
   const int l = lane_id();
-  f32x4 acc[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) acc[mt] = relu4(M::mma(w[(mt * 3 + 0) * 64 + l], b0, pre[mt]));
-  const vec *wl = w + 12 * 64;
   for (int h = 1; h < hidden; ++h) {
     float t0[8], t1[8];
 #pragma unroll
@@ -309,6 +415,17 @@ __device__ __forceinline__ f32x4 mlp_rest16(const typename Mma<P>::vec *__restri
 }
 
 template <int P>
+__device__ __forceinline__ f32x4 mlp_rest16(const typename Mma<P>::vec *__restrict__ w, int hidden,
+                                            typename Mma<P>::vec b0, const f32x4 pre[4]) {
+  typedef Mma<P> M;
+  const int l = lane_id();
+  f32x4 acc[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) acc[mt] = relu4(M::mma(w[(mt * 3 + 0) * 64 + l], b0, pre[mt]));
+  return mlp_tail16<P>(w + 12 * 64, hidden, acc);
+}
+
+template <int P>
 __device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__restrict__ w,
                                                int hidden, typename Mma<P>::vec b0,
                                                typename Mma<P>::vec b1, typename Mma<P>::vec b2) {
@@ -320,24 +437,9 @@ __device__ __forceinline__ f32x4 mlp_forward16(const typename Mma<P>::vec *__res
 // FP32 variant on v_mfma_f32_16x16x4f32: one K=4 chunk per instruction; chunk c of the input
 // layer carries, in lane group q, position feature 8q+c (c < 8), direction feature 8q+c-8
 // (c < 16) or g (c = 16, q = 0); hidden chunk (t, r) carries neuron 16t+4q+r.
-__device__ __forceinline__ f32x4 mlp_forward16_f32(const float *__restrict__ w, int hidden,
-                                                   const float pos[8], const float dir[8],
-                                                   float gin) {
+__device__ __forceinline__ f32x4 mlp_tail16_f32(const float *__restrict__ wl, int hidden,
+                                                f32x4 acc[4]) {
   const int l = lane_id();
-  f32x4 acc[4];
-#pragma unroll
-  for (int mt = 0; mt < 4; ++mt) {
-    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
-    const float *wm = w + mt * 17 * 64 + l;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[c * 64], pos[c], a, 0, 0, 0);
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 + c) * 64], dir[c], a, 0, 0, 0);
-    a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * 64], gin, a, 0, 0, 0);
-    acc[mt] = relu4(a);
-  }
-  const float *wl = w + 4 * 17 * 64;
   for (int h = 1; h < hidden; ++h) {
     f32x4 nxt[4];
 #pragma unroll
@@ -364,6 +466,103 @@ __device__ __forceinline__ f32x4 mlp_forward16_f32(const float *__restrict__ w, 
   return out;
 }
 
+__device__ __forceinline__ f32x4 mlp_forward16_f32(const float *__restrict__ w, int hidden,
+                                                   const float pos[8], const float dir[8],
+                                                   float gin) {
+  const int l = lane_id();
+  f32x4 acc[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+    const float *wm = w + mt * 17 * 64 + l;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[c * 64], pos[c], a, 0, 0, 0);
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 + c) * 64], dir[c], a, 0, 0, 0);
+    a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * 64], gin, a, 0, 0, 0);
+    acc[mt] = relu4(a);
+  }
+  return mlp_tail16_f32(w + 4 * 17 * 64, hidden, acc);
+}
+
+// ---------------- FG feature groups (FG = 1: the functions above).  Per 16-row tile the input
+// layer's 16-bit image holds C = 2 FG + 1 chunks (position groups, direction groups, g); the FP32
+// image 16 FG + 1 chunks (8 per position group, 8 per direction group, g).
+template <int P, int FG>
+__device__ __forceinline__ void mlp_input16_g(const typename Mma<P>::vec *__restrict__ w,
+                                              const typename Mma<P>::vec (&b1)[FG],
+                                              typename Mma<P>::vec b2, f32x4 pre[4]) {
+  if constexpr (FG == 1) {
+    mlp_input16<P>(w, b1[0], b2, pre);
+  } else {
+    typedef Mma<P> M;
+    constexpr int C = 2 * FG + 1;
+    const int l = lane_id();
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int g = 0; g < FG; ++g) a = M::mma(w[(mt * C + FG + g) * 64 + l], b1[g], a);
+      pre[mt] = M::mma(w[(mt * C + 2 * FG) * 64 + l], b2, a);
+    }
+  }
+}
+
+template <int P, int FG>
+__device__ __forceinline__ f32x4 mlp_rest16_g(const typename Mma<P>::vec *__restrict__ w,
+                                              int hidden, const typename Mma<P>::vec (&b0)[FG],
+                                              const f32x4 pre[4]) {
+  if constexpr (FG == 1) {
+    return mlp_rest16<P>(w, hidden, b0[0], pre);
+  } else {
+    typedef Mma<P> M;
+    constexpr int C = 2 * FG + 1;
+    const int l = lane_id();
+    f32x4 acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = pre[mt];
+#pragma unroll
+      for (int g = 0; g < FG; ++g) a = M::mma(w[(mt * C + g) * 64 + l], b0[g], a);
+      acc[mt] = relu4(a);
+    }
+    return mlp_tail16<P>(w + 4 * C * 64, hidden, acc);
+  }
+}
+
+template <int FG>
+__device__ __forceinline__ f32x4 mlp_forward16_f32_g(const float *__restrict__ w, int hidden,
+                                                     const float (&pos)[FG][8],
+                                                     const float (&dir)[FG][8], float gin) {
+  if constexpr (FG == 1) {
+    return mlp_forward16_f32(w, hidden, pos[0], dir[0], gin);
+  } else {
+    constexpr int C = 16 * FG + 1;
+    const int l = lane_id();
+    f32x4 acc[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+      f32x4 a = {0.0f, 0.0f, 0.0f, 0.0f};
+      const float *wm = w + mt * C * 64 + l;
+#pragma unroll
+      for (int g = 0; g < FG; ++g)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 * g + c) * 64], pos[g][c], a, 0, 0, 0);
+#pragma unroll
+      for (int g = 0; g < FG; ++g)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 * FG + 8 * g + c) * 64], dir[g][c], a, 0,
+                                                   0, 0);
+      a = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * FG * 64], gin, a, 0, 0, 0);
+      acc[mt] = relu4(a);
+    }
+    return mlp_tail16_f32(w + 4 * C * 64, hidden, acc);
+  }
+}
+
 // One 16-query tile: encode (lane group q computes levels 4q..4q+3 of query l%16) and run the
 // MLP.  Returns the output tile (lanes 0..15: L' of query l).
 template <int P>
@@ -380,6 +579,37 @@ __device__ __forceinline__ f32x4 field_tile16(const FieldDev &F, const void *__r
     float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
     return mlp_forward16<P>(reinterpret_cast<const typename M::vec *>(lds_w), F.hidden,
                             M::pack(pos), M::pack(dir), M::pack(gz));
+  }
+}
+
+template <int P, int FG>
+__device__ __forceinline__ f32x4 field_tile16_g(const FieldDev &F, const void *__restrict__ lds_w,
+                                                f3 x, float u0, float u1, float g, bool valid) {
+  if constexpr (FG == 1) {
+    return field_tile16<P>(F, lds_w, x, u0, u1, g, valid);
+  } else {
+    const int q = lane_id() >> 4;
+    float pos[FG][8], dir[FG][8];
+    encode_lane_g<P, FG>(F, q, clamp01(x), u0, u1, valid, pos, dir);
+    const float gin = (q == 0) ? g : 0.0f;
+    if constexpr (P == P_F32) {
+      return mlp_forward16_f32_g<FG>(reinterpret_cast<const float *>(lds_w), F.hidden, pos, dir,
+                                     gin);
+    } else {
+      typedef Mma<P> M;
+      typedef typename M::vec vec;
+      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+      vec b0[FG], b1[FG];
+#pragma unroll
+      for (int gi = 0; gi < FG; ++gi) {
+        b0[gi] = M::pack(pos[gi]);
+        b1[gi] = M::pack(dir[gi]);
+      }
+      const vec *w = reinterpret_cast<const vec *>(lds_w);
+      f32x4 pre[4];
+      mlp_input16_g<P, FG>(w, b1, M::pack(gz), pre);
+      return mlp_rest16_g<P, FG>(w, F.hidden, b0, pre);
+    }
   }
 }
 

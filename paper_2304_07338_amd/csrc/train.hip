@@ -126,20 +126,28 @@ __global__ void train_batch_kernel(SampleSrc s, int64_t n, float *xyz, float *di
 struct BwdPackArgs {
   const float *w[PFN_MAX_HIDDEN + 1];
   int hidden, levels, n_in;
+  int fg;  // feature groups (features per level / 2)
 };
 
-__host__ __device__ constexpr int bwd_elems(int prec, int hidden) {
-  return prec == P_F32 ? (4 * 64 + (hidden - 1) * 4 * 16 * 64 + 4 * 16 * 64)
-                       : (4 * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 4 * 2 * 64 * 8);
+// firstT has 4 row tiles per feature group: position slots 0-3 and 4-7, direction slots 0-3 and
+// 4-7 of the group's lane-group layout.
+__host__ __device__ constexpr int bwd_elems(int prec, int hidden, int fg = 1) {
+  return prec == P_F32 ? (4 * 64 + (hidden - 1) * 4 * 16 * 64 + 4 * fg * 16 * 64)
+                       : (4 * 64 * 8 + (hidden - 1) * 4 * 2 * 64 * 8 + 4 * fg * 2 * 64 * 8);
 }
 
-// Input column of W_0 whose gradient lands in row rho of row tile mt (-1: none).
+// Input column of W_0 whose gradient lands in row rho of row tile mt (-1: none).  Tile mt
+// belongs to feature group mt / 4; within it, tiles 0/1 hold position slots 0-3 / 4-7 and tiles
+// 2/3 direction slots 0-3 / 4-7, slot s of lane group qq being feature 2 grp + (s & 1) of level
+// 4 qq + s / 2.
 __device__ __forceinline__ int first_row_col(const BwdPackArgs &a, int mt, int rho) {
+  const int grp = mt >> 2, sub = mt & 3;
   int qq = rho >> 2, r = rho & 3;
-  int feat = 8 * qq + ((mt & 1) ? 4 : 0) + r;  // feature slot of lane group qq
+  int feat = 8 * qq + ((sub & 1) ? 4 : 0) + r;  // feature slot of lane group qq
   int lv = feat >> 1, f = feat & 1;
   if (lv >= a.levels) return -1;
-  return (mt < 2 ? 0 : 2 * a.levels) + 2 * lv + f;
+  const int F = 2 * a.fg;
+  return (sub < 2 ? 0 : F * a.levels) + F * lv + 2 * grp + f;
 }
 __device__ __forceinline__ int hid_col_b(int c, int q, int i) {
   return i < 4 ? 32 * c + 4 * q + i : 32 * c + 16 + 4 * q + (i - 4);
@@ -200,8 +208,9 @@ hipError_t launch_field_pack_bwd(pfn_context *ctx, FieldSlot &f, int prec) {
   for (int m = 0; m <= f.desc.hidden_layers; ++m) a.w[m] = f.master + f.w_off[m];
   a.hidden = f.desc.hidden_layers;
   a.levels = f.desc.levels;
-  a.n_in = 4 * f.desc.levels + 1;
-  int total = bwd_elems(prec, a.hidden);
+  a.fg = f.desc.feats_per_level / 2;
+  a.n_in = 2 * f.desc.feats_per_level * f.desc.levels + 1;
+  int total = bwd_elems(prec, a.hidden, a.fg);
   unsigned blocks = (unsigned)((total + 255) / 256);
   if (prec == P_F32)
     hipLaunchKernelGGL(pack_bwd32_kernel, dim3(blocks), dim3(256), 0, ctx->stream, a,
@@ -263,15 +272,18 @@ struct ActT<P_F32> {
 // of lanes: lanes of one instruction that hit one 64-byte segment share a request.  A lane
 // therefore does not scatter its own sample's corners (every lane a different segment); the wave
 // stages its 16 samples' encoder gradients in LDS and scatters them with a lane mapping in which
-// the 4 floats of an x-neighbour corner pair (2 features of corner x0, 2 of corner x1: one
-// 16-byte run on dense levels, and on hashed levels whenever x0 is even, since the hash's
-// x prime is 1) come from 4 consecutive lanes.
+// the floats of an x-neighbour corner pair (the features of corner x0, then of corner x1: one
+// run on dense levels, and on hashed levels whenever x0 is even, since the hash's x prime is 1)
+// come from consecutive lanes: 4 lanes per pair with 2 features per level, 16 with 8.
 #define TRAIN_WAVES (TRAIN_THREADS / 64)
-#define DZ_STRIDE 65  // floats per staged sample (64 gradients, padded against bank conflicts)
 
+// Staged gradients of one wave: per sample, position features at F lv + c and direction
+// features at 16 F + F lv + c (F = 2 FG features per level), padded against bank conflicts.
+template <int FG>
 struct StagedGrads {
-  float dz[TRAIN_WAVES][16][DZ_STRIDE];  // [wave][sample][2L position, then 2L direction]
-  float xu[TRAIN_WAVES][16][6];          // x, y, z, u0, u1, valid
+  static constexpr int STRIDE = 64 * FG + 1;
+  float dz[TRAIN_WAVES][16][STRIDE];
+  float xu[TRAIN_WAVES][16][6];  // x, y, z, u0, u1, valid
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -280,17 +292,23 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Lane (q, nl) holds the gradients of sample nl for levels 4q..4q+3: position gp[2j + f] and
-// direction gd[2j + f] of level 4q + j, feature f.
-__device__ __forceinline__ void stage_grid_grads(StagedGrads &S, int wv, int q, int nl, bool valid,
-                                                 f3 x, float u0, float u1, const float gp[8],
-                                                 const float gd[8]) {
+// Lane (q, nl) holds the gradients of sample nl for levels 4q..4q+3: position gp[g][2j + f] and
+// direction gd[g][2j + f] of level 4q + j, feature 2g + f.
+template <int FG>
+__device__ __forceinline__ void stage_grid_grads(StagedGrads<FG> &S, int wv, int q, int nl,
+                                                 bool valid, f3 x, float u0, float u1,
+                                                 const float (&gp)[FG][8],
+                                                 const float (&gd)[FG][8]) {
+  constexpr int F = 2 * FG;
   float *d = S.dz[wv][nl];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    d[8 * q + r] = valid ? gp[r] : 0.0f;
-    d[32 + 8 * q + r] = valid ? gd[r] : 0.0f;
-  }
+  for (int g = 0; g < FG; ++g)
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int c = F * (4 * q + (s >> 1)) + 2 * g + (s & 1);
+      d[c] = valid ? gp[g][s] : 0.0f;
+      d[16 * F + c] = valid ? gd[g][s] : 0.0f;
+    }
   if (q == 0) {
     float *c = S.xu[wv][nl];
     c[0] = x.x;
@@ -302,63 +320,87 @@ __device__ __forceinline__ void stage_grid_grads(StagedGrads &S, int wv, int q, 
   }
 }
 
-__device__ __forceinline__ void scatter_staged(const TrainArgs &a, const StagedGrads &S, int wv,
-                                               int lane) {
+// One corner of level lv for a staged sample: entry index and trilinear (bilinear) weight.
+__device__ __forceinline__ void pos_corner(const FieldDev &F, int lv, const float *xu, int xb,
+                                           int cp, uint32_t &idx, float &w) {
+  const int N = F.pos.res[lv];
+  const bool dense = (F.pos.dense_mask >> lv) & 1u;
+  int cx, cy, cz;
+  float fx, fy, fz;
+  level_cell(xu[0], N, cx, fx);
+  level_cell(xu[1], N, cy, fy);
+  level_cell(xu[2], N, cz, fz);
+  const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + (cp & 1)),
+                 vz = (uint32_t)(cz + (cp >> 1));
+  const uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
+  idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
+  w = (xb ? fx : 1.0f - fx) * ((cp & 1) ? fy : 1.0f - fy) * ((cp >> 1) ? fz : 1.0f - fz);
+}
+__device__ __forceinline__ void dir_corner(const FieldDev &F, int lv, const float *xu, int xb,
+                                           int cp, uint32_t &idx, float &w) {
+  const int N = F.dir.res[lv];
+  const bool dense = (F.dir.dense_mask >> lv) & 1u;
+  int cx, cy;
+  float fx, fy;
+  level_cell(xu[3], N, cx, fx);
+  level_cell(xu[4], N, cy, fy);
+  const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + cp);
+  const uint32_t s1 = (uint32_t)(N + 1);
+  idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
+  w = (xb ? fx : 1.0f - fx) * (cp ? fy : 1.0f - fy);
+}
+
+template <int FG>
+__device__ __forceinline__ void scatter_staged(const TrainArgs &a, const StagedGrads<FG> &S,
+                                               int wv, int lane) {
   const FieldDev &F = a.F;
-  // position levels: 16 lanes per (level, sample), 4 (level, sample) pairs per instruction
+  constexpr int NF = 2 * FG;  // features per level
+  // lanes per (level, sample): position 4 corner pairs x 2 corners x NF features, direction 2
+  // pairs x 2 x NF; consecutive lanes run over the features, then the pair's two corners
+  constexpr int PL = 8 * NF, DL = 4 * NF;
   {
-    const int r = lane & 15, cp = r >> 2, xb = (r >> 1) & 1, feat = r & 1;
-    const int smp4 = lane >> 4;
+    const int r = lane % PL, cp = r / (2 * NF), xb = (r / NF) & 1, feat = r % NF;
+    const int sub = lane / PL;  // sample within the instruction
+    constexpr int PER = 64 / PL;
 #pragma unroll 1
-    for (int it = 0; it < 4 * F.levels; ++it) {
-      const int lv = it >> 2, smp = 4 * (it & 3) + smp4;
+    for (int it = 0; it < (16 / PER) * F.levels; ++it) {
+      const int lv = it / (16 / PER), smp = PER * (it % (16 / PER)) + sub;
       const float *xu = S.xu[wv][smp];
-      const float gv = S.dz[wv][smp][2 * lv + feat];
+      const float gv = S.dz[wv][smp][NF * lv + feat];
       if (xu[5] == 0.0f) continue;
-      const int N = F.pos.res[lv];
-      const uint32_t off = F.pos.off[lv];
-      const bool dense = (F.pos.dense_mask >> lv) & 1u;
-      int cx, cy, cz;
-      float fx, fy, fz;
-      level_cell(xu[0], N, cx, fx);
-      level_cell(xu[1], N, cy, fy);
-      level_cell(xu[2], N, cz, fz);
-      const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + (cp & 1)),
-                     vz = (uint32_t)(cz + (cp >> 1));
-      const uint32_t s1 = (uint32_t)(N + 1), s2 = s1 * s1;
-      const uint32_t idx = dense ? (vx + vy * s1 + vz * s2) : (hash3(vx, vy, vz) & F.hash_mask);
-      const float w = (xb ? fx : 1.0f - fx) * ((cp & 1) ? fy : 1.0f - fy) *
-                      ((cp >> 1) ? fz : 1.0f - fz);
-      atomicAdd(a.grad_pos + 2 * (size_t)(off + idx) + feat, w * gv);
+      uint32_t idx;
+      float w;
+      pos_corner(F, lv, xu, xb, cp, idx, w);
+      atomicAdd(a.grad_pos + (size_t)NF * (F.pos.off[lv] + idx) + feat, w * gv);
     }
   }
-  // direction levels: 8 lanes per (level, sample), 8 pairs per instruction
   {
-    const int r = lane & 7, cp = r >> 2, xb = (r >> 1) & 1, feat = r & 1;
-    const int smp8 = lane >> 3;
+    const int r = lane % DL, cp = r / (2 * NF), xb = (r / NF) & 1, feat = r % NF;
+    const int sub = lane / DL;
+    constexpr int PER = 64 / DL;
 #pragma unroll 1
-    for (int it = 0; it < 2 * F.levels; ++it) {
-      const int lv = it >> 1, smp = 8 * (it & 1) + smp8;
+    for (int it = 0; it < (16 / PER) * F.levels; ++it) {
+      const int lv = it / (16 / PER), smp = PER * (it % (16 / PER)) + sub;
       const float *xu = S.xu[wv][smp];
-      const float gv = S.dz[wv][smp][32 + 2 * lv + feat];
+      const float gv = S.dz[wv][smp][16 * NF + NF * lv + feat];
       if (xu[5] == 0.0f) continue;
-      const int N = F.dir.res[lv];
-      const uint32_t off = F.dir.off[lv];
-      const bool dense = (F.dir.dense_mask >> lv) & 1u;
-      int cx, cy;
-      float fx, fy;
-      level_cell(xu[3], N, cx, fx);
-      level_cell(xu[4], N, cy, fy);
-      const uint32_t vx = (uint32_t)(cx + xb), vy = (uint32_t)(cy + cp);
-      const uint32_t s1 = (uint32_t)(N + 1);
-      const uint32_t idx = dense ? (vx + vy * s1) : (hash2(vx, vy) & F.hash_mask);
-      const float w = (xb ? fx : 1.0f - fx) * (cp ? fy : 1.0f - fy);
-      atomicAdd(a.grad_dir + 2 * (size_t)(off + idx) + feat, w * gv);
+      uint32_t idx;
+      float w;
+      dir_corner(F, lv, xu, xb, cp, idx, w);
+      atomicAdd(a.grad_dir + (size_t)NF * (F.dir.off[lv] + idx) + feat, w * gv);
     }
   }
 }
 
-template <int P, int H, bool GEN>
+// Row of the layer-0 input matrix (the network input index) of slot s of feature group g in lane
+// group q: position features F lv + c, direction features F L + F lv + c, g at 2 F L.
+template <int FG>
+__device__ __forceinline__ int in_row(int L, int q, int g, int s, bool dir) {
+  constexpr int F = 2 * FG;
+  return (dir ? F * L : 0) + F * (4 * q + (s >> 1)) + 2 * g + (s & 1);
+}
+
+template <int P, int H, bool GEN, int FG>
 __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
   typedef typename ActT<P>::type T;
   // One 16-sample tile per wave and no loop over tiles: the weight operands are then not
@@ -368,8 +410,9 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
   const int64_t tile = (int64_t)blockIdx.x * TRAIN_WAVES + wv;
   const int64_t ntiles = a.ldn / 16;
   const int L = a.F.levels;
+  constexpr int NF = 2 * FG;
   T *act = reinterpret_cast<T *>(a.act);
-  __shared__ StagedGrads S;
+  __shared__ StagedGrads<FG> S;
   double wave_loss = 0.0;
   if (tile < ntiles) {
     const int64_t i = tile * 16 + nl;
@@ -392,42 +435,54 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
     x = clamp01(x);
     float u0, u1;
     dir_coords(w, u0, u1);
-    float pos[8], dir[8];
-    encode_lane<P>(a.F, q, x, u0, u1, valid, pos, dir);
+    float pos[FG][8], dir[FG][8];
+    encode_lane_g<P, FG>(a.F, q, x, u0, u1, valid, pos, dir);
     const float gin = (q == 0) ? g : 0.0f;
 
     // layer-0 inputs (rows = network input index)
     {
       T *in0 = act + a.in_off[0];
 #pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        int lv = 4 * q + (s >> 1);
-        if (lv < L) {
-          in0[(int64_t)(2 * lv + (s & 1)) * a.ldn + i] = to_t<T>(valid ? pos[s] : 0.f);
-          in0[(int64_t)(2 * L + 2 * lv + (s & 1)) * a.ldn + i] = to_t<T>(valid ? dir[s] : 0.f);
+      for (int gr = 0; gr < FG; ++gr)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          int lv = 4 * q + (s >> 1);
+          if (lv < L) {
+            in0[(int64_t)in_row<FG>(L, q, gr, s, false) * a.ldn + i] =
+                to_t<T>(valid ? pos[gr][s] : 0.f);
+            in0[(int64_t)in_row<FG>(L, q, gr, s, true) * a.ldn + i] =
+                to_t<T>(valid ? dir[gr][s] : 0.f);
+          }
         }
-      }
-      if (q == 0) in0[(int64_t)(4 * L) * a.ldn + i] = to_t<T>(valid ? g : 0.f);
+      if (q == 0) in0[(int64_t)(2 * NF * L) * a.ldn + i] = to_t<T>(valid ? g : 0.f);
     }
 
     float e[3], lsum[3];
+    f32x4 dz[4 * FG];  // gradients of the encoder outputs (firstT row tiles)
     if constexpr (P == P_F32) {
       const float *W = reinterpret_cast<const float *>(a.fwd);
       const float *B = reinterpret_cast<const float *>(a.bwd);
+      constexpr int C = 16 * FG + 1;
       f32x4 hv[H][4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
-        const float *wm = W + mt * 17 * 64 + lane;
+        const float *wm = W + mt * C * 64 + lane;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[k * 64], pos[k], c, 0, 0, 0);
+        for (int gr = 0; gr < FG; ++gr)
 #pragma unroll
-        for (int k = 0; k < 8; ++k)
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 + k) * 64], dir[k], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * 64], gin, c, 0, 0, 0);
+          for (int k = 0; k < 8; ++k)
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 * gr + k) * 64], pos[gr][k], c, 0, 0, 0);
+#pragma unroll
+        for (int gr = 0; gr < FG; ++gr)
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(8 * FG + 8 * gr + k) * 64], dir[gr][k], c,
+                                                     0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[16 * FG * 64], gin, c, 0, 0, 0);
         hv[0][mt] = relu4(c);
       }
-      const float *wl = W + 4 * 17 * 64;
+      const float *wl = W + 4 * C * 64;
 #pragma unroll
       for (int k = 1; k < H; ++k) {
 #pragma unroll
@@ -488,51 +543,64 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
             ib[ro] = to_t<T>(h);
             db[ro] = to_t<T>(acc[t][r]);
           }
-        const float *img = (k >= 1) ? bh + (k - 1) * 4 * 16 * 64 : bh + (H - 1) * 4 * 16 * 64;
-        f32x4 nxt[4];
+        if (k >= 1) {
+          const float *img = bh + (k - 1) * 4 * 16 * 64;
+          f32x4 nxt[4];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          f32x4 c = {0.f, 0.f, 0.f, 0.f};
-          const float *wm = img + mt * 16 * 64 + lane;
+          for (int mt = 0; mt < 4; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            const float *wm = img + mt * 16 * 64 + lane;
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], acc[t][r], c, 0, 0, 0);
-          nxt[mt] = c;
+              for (int r = 0; r < 4; ++r)
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], acc[t][r], c, 0, 0, 0);
+            nxt[mt] = c;
+          }
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt) acc[mt] = nxt[mt];
+        } else {
+          const float *img = bh + (H - 1) * 4 * 16 * 64;  // firstT
+#pragma unroll
+          for (int mt = 0; mt < 4 * FG; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            const float *wm = img + mt * 16 * 64 + lane;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+                c = __builtin_amdgcn_mfma_f32_16x16x4f32(wm[(t * 4 + r) * 64], acc[t][r], c, 0, 0, 0);
+            dz[mt] = c;
+          }
         }
-#pragma unroll
-        for (int mt = 0; mt < 4; ++mt) acc[mt] = nxt[mt];
-      }
-      {
-        float gp[8], gd[8];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          gp[r] = acc[0][r];
-          gp[4 + r] = acc[1][r];
-          gd[r] = acc[2][r];
-          gd[4 + r] = acc[3][r];
-        }
-        stage_grid_grads(S, wv, q, nl, valid, x, u0, u1, gp, gd);
       }
     } else {
       typedef Mma<P> M;
       typedef typename M::vec vec;
+      constexpr int C = 2 * FG + 1;
       const vec *W = reinterpret_cast<const vec *>(a.fwd);
       const vec *B = reinterpret_cast<const vec *>(a.bwd);
       float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
-      vec b0 = M::pack(pos), b1 = M::pack(dir), b2 = M::pack(gz);
+      vec b0[FG], b1[FG];
+#pragma unroll
+      for (int gr = 0; gr < FG; ++gr) {
+        b0[gr] = M::pack(pos[gr]);
+        b1[gr] = M::pack(dir[gr]);
+      }
+      const vec b2 = M::pack(gz);
       vec hv[H][2];
       f32x4 acc[4];
 #pragma unroll
       for (int mt = 0; mt < 4; ++mt) {
         f32x4 c = {0.f, 0.f, 0.f, 0.f};
-        c = M::mma(W[(mt * 3 + 0) * 64 + lane], b0, c);
-        c = M::mma(W[(mt * 3 + 1) * 64 + lane], b1, c);
-        c = M::mma(W[(mt * 3 + 2) * 64 + lane], b2, c);
+#pragma unroll
+        for (int gr = 0; gr < FG; ++gr) c = M::mma(W[(mt * C + gr) * 64 + lane], b0[gr], c);
+#pragma unroll
+        for (int gr = 0; gr < FG; ++gr) c = M::mma(W[(mt * C + FG + gr) * 64 + lane], b1[gr], c);
+        c = M::mma(W[(mt * C + 2 * FG) * 64 + lane], b2, c);
         acc[mt] = relu4(c);
       }
-      const vec *wl = W + 12 * 64;
+      const vec *wl = W + 4 * C * 64;
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         float t0[8], t1[8];
@@ -605,29 +673,42 @@ __global__ __launch_bounds__(TRAIN_THREADS) void train_fb_kernel(TrainArgs a) {
             db[ro] = to_t<T>(dv);
           }
         vec bd0 = M::pack(dt[0]), bd1 = M::pack(dt[1]);
-        const vec *img = (k >= 1) ? bh + (k - 1) * 8 * 64 : bh + (H - 1) * 8 * 64;
+        if (k >= 1) {
+          const vec *img = bh + (k - 1) * 8 * 64;
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-          f32x4 c = {0.f, 0.f, 0.f, 0.f};
-          c = M::mma(img[(mt * 2 + 0) * 64 + lane], bd0, c);
-          c = M::mma(img[(mt * 2 + 1) * 64 + lane], bd1, c);
-          acc[mt] = c;
-        }
-      }
-      {
-        float gp[8], gd[8];
+          for (int mt = 0; mt < 4; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            c = M::mma(img[(mt * 2 + 0) * 64 + lane], bd0, c);
+            c = M::mma(img[(mt * 2 + 1) * 64 + lane], bd1, c);
+            acc[mt] = c;
+          }
+        } else {
+          const vec *img = bh + (H - 1) * 8 * 64;  // firstT
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          gp[r] = acc[0][r];
-          gp[4 + r] = acc[1][r];
-          gd[r] = acc[2][r];
-          gd[4 + r] = acc[3][r];
+          for (int mt = 0; mt < 4 * FG; ++mt) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            c = M::mma(img[(mt * 2 + 0) * 64 + lane], bd0, c);
+            c = M::mma(img[(mt * 2 + 1) * 64 + lane], bd1, c);
+            dz[mt] = c;
+          }
         }
-        stage_grid_grads(S, wv, q, nl, valid, x, u0, u1, gp, gd);
       }
     }
+    {
+      float gp[FG][8], gd[FG][8];
+#pragma unroll
+      for (int gr = 0; gr < FG; ++gr)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          gp[gr][r] = dz[4 * gr + 0][r];
+          gp[gr][4 + r] = dz[4 * gr + 1][r];
+          gd[gr][r] = dz[4 * gr + 2][r];
+          gd[gr][4 + r] = dz[4 * gr + 3][r];
+        }
+      stage_grid_grads<FG>(S, wv, q, nl, valid, x, u0, u1, gp, gd);
+    }
     wave_sync_lds();
-    scatter_staged(a, S, wv, lane);
+    scatter_staged<FG>(a, S, wv, lane);
     if (q == 0) wave_loss += (double)lsum[0] + (double)lsum[1] + (double)lsum[2];
   }
   for (int off = 32; off > 0; off >>= 1) wave_loss += __shfl_down(wave_loss, off);
@@ -732,7 +813,8 @@ struct TrainLayout {
   int64_t elems;
 };
 
-static TrainLayout train_layout(int H, int64_t n) {
+// in0_rows: rows of the layer-0 input matrix (the network input padded to 16-row tiles)
+static TrainLayout train_layout(int H, int64_t n, int in0_rows) {
   TrainLayout t{};
   t.ldn = (n + 31) / 32 * 32;
   int64_t off = 0;
@@ -742,14 +824,17 @@ static TrainLayout train_layout(int H, int64_t n) {
   }
   for (int m = 0; m <= H; ++m) {
     t.in_off[m] = off;
-    off += (int64_t)(m == 0 ? 80 : 64) * t.ldn;
+    off += (int64_t)(m == 0 ? in0_rows : 64) * t.ldn;
   }
   t.elems = off;
   return t;
 }
 
+static int n_inputs(const FieldSlot &f) { return 2 * f.desc.feats_per_level * f.desc.levels + 1; }
+static int in0_rows(const FieldSlot &f) { return std::max(80, (n_inputs(f) + 15) / 16 * 16); }
+
 static pfn_status ensure_train_buffers(pfn_context *ctx, FieldSlot &f, int prec, int64_t n) {
-  TrainLayout tl = train_layout(f.desc.hidden_layers, n);
+  TrainLayout tl = train_layout(f.desc.hidden_layers, n, in0_rows(f));
   size_t bytes = (size_t)tl.elems * (prec == P_F32 ? 4 : 2);
   if (ctx->train_act_bytes < bytes) {
     if (ctx->train_act) (void)hipFree(ctx->train_act);
@@ -761,7 +846,8 @@ static pfn_status ensure_train_buffers(pfn_context *ctx, FieldSlot &f, int prec,
   PFN_HIP(ctx, hipMemsetAsync(ctx->train_act, 0, bytes, ctx->stream));
   if (!f.mlp_bwd[prec]) {
     PFN_HIP(ctx, hipMalloc(&f.mlp_bwd[prec],
-                           (size_t)bwd_elems(prec, f.desc.hidden_layers) * (prec == P_F32 ? 4 : 2)));
+                           (size_t)bwd_elems(prec, f.desc.hidden_layers, f.desc.feats_per_level / 2) *
+                               (prec == P_F32 ? 4 : 2)));
   }
   return PFN_OK;
 }
@@ -776,27 +862,35 @@ static pfn_status refresh_train_images(pfn_context *ctx, FieldSlot &f, int prec)
   return PFN_OK;
 }
 
-template <int P, int H, bool GEN>
+template <int P, int H, bool GEN, int FG>
 static hipError_t launch_fb_t(const TrainArgs &a, unsigned blocks, hipStream_t st) {
-  hipLaunchKernelGGL((train_fb_kernel<P, H, GEN>), dim3(blocks), dim3(TRAIN_THREADS), 0, st, a);
+  hipLaunchKernelGGL((train_fb_kernel<P, H, GEN, FG>), dim3(blocks), dim3(TRAIN_THREADS), 0, st,
+                     a);
   return hipGetLastError();
 }
-template <int P, bool GEN>
+template <int P, bool GEN, int FG>
 static hipError_t launch_fb_h(const TrainArgs &a, int H, unsigned blocks, hipStream_t st) {
   switch (H) {
-    case 1: return launch_fb_t<P, 1, GEN>(a, blocks, st);
-    case 2: return launch_fb_t<P, 2, GEN>(a, blocks, st);
-    case 3: return launch_fb_t<P, 3, GEN>(a, blocks, st);
-    case 4: return launch_fb_t<P, 4, GEN>(a, blocks, st);
-    case 5: return launch_fb_t<P, 5, GEN>(a, blocks, st);
+    case 1: return launch_fb_t<P, 1, GEN, FG>(a, blocks, st);
+    case 2: return launch_fb_t<P, 2, GEN, FG>(a, blocks, st);
+    case 3: return launch_fb_t<P, 3, GEN, FG>(a, blocks, st);
+    case 4: return launch_fb_t<P, 4, GEN, FG>(a, blocks, st);
+    case 5: return launch_fb_t<P, 5, GEN, FG>(a, blocks, st);
     default: return hipErrorInvalidValue;
   }
 }
+template <bool GEN, int FG>
+static hipError_t launch_fb_p(const TrainArgs &a, int prec, int H, unsigned blocks,
+                              hipStream_t st) {
+  if (prec == P_F32) return launch_fb_h<P_F32, GEN, FG>(a, H, blocks, st);
+  if (prec == P_BF16) return launch_fb_h<P_BF16, GEN, FG>(a, H, blocks, st);
+  return launch_fb_h<P_F16, GEN, FG>(a, H, blocks, st);
+}
 template <bool GEN>
-static hipError_t launch_fb(const TrainArgs &a, int prec, int H, unsigned blocks, hipStream_t st) {
-  if (prec == P_F32) return launch_fb_h<P_F32, GEN>(a, H, blocks, st);
-  if (prec == P_BF16) return launch_fb_h<P_BF16, GEN>(a, H, blocks, st);
-  return launch_fb_h<P_F16, GEN>(a, H, blocks, st);
+static hipError_t launch_fb(const TrainArgs &a, int prec, int H, int fg, unsigned blocks,
+                            hipStream_t st) {
+  return fg == 1 ? launch_fb_p<GEN, 1>(a, prec, H, blocks, st)
+                 : launch_fb_p<GEN, 4>(a, prec, H, blocks, st);
 }
 
 // Forward/backward over n samples into f.grad (unscaled), loss sum into *loss_dev.
@@ -804,7 +898,8 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
                          const SampleSrc &src, const float *xyz, const float *dir, const float *g,
                          const float *tgt, double *loss_dev, int rel_loss) {
   const int H = f.desc.hidden_layers;
-  TrainLayout tl = train_layout(H, n);
+  const int fg = f.desc.feats_per_level / 2;
+  TrainLayout tl = train_layout(H, n, in0_rows(f));
   TrainArgs a{};
   a.F = make_field_dev(f, prec);
   a.fwd = f.mlp_packed[prec];
@@ -817,7 +912,7 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
   a.n = n;
   a.ldn = tl.ldn;
   a.grad_pos = f.grad;
-  a.grad_dir = f.grad + 2 * f.pos_entries;
+  a.grad_dir = f.grad + (size_t)f.desc.feats_per_level * f.pos_entries;
   a.act = ctx->train_act;
   for (int m = 0; m <= H; ++m) {
     a.delta_off[m] = tl.delta_off[m];
@@ -828,8 +923,8 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
   int64_t ntiles = tl.ldn / 16;
   unsigned blocks = (unsigned)((ntiles + 3) / 4);
   const int tslot = timing_begin(ctx);
-  PFN_HIP(ctx, gen ? launch_fb<true>(a, prec, H, blocks, ctx->stream)
-                   : launch_fb<false>(a, prec, H, blocks, ctx->stream));
+  PFN_HIP(ctx, gen ? launch_fb<true>(a, prec, H, fg, blocks, ctx->stream)
+                   : launch_fb<false>(a, prec, H, fg, blocks, ctx->stream));
   timing_end(ctx, tslot, TK_TRAIN);
   // weight gradients, one launch per layer
   const int kchunk = 2048;
@@ -841,10 +936,10 @@ static pfn_status run_fb(pfn_context *ctx, FieldSlot &f, int prec, int64_t n, bo
     d.in_off = tl.in_off[m];
     d.kchunk = kchunk;
     d.rows = m == H ? 3 : PFN_WIDTH;
-    d.cols = m == 0 ? 4 * f.desc.levels + 1 : PFN_WIDTH;
+    d.cols = m == 0 ? n_inputs(f) : PFN_WIDTH;
     d.grad = f.grad + f.w_off[m];
     d.n_ot = m == H ? 1 : 4;
-    d.n_it = m == 0 ? 5 : 4;
+    d.n_it = m == 0 ? in0_rows(f) / 16 : 4;
     dim3 grid((unsigned)((tl.ldn + kchunk - 1) / kchunk), (unsigned)(d.n_ot * d.n_it));
     if (prec == P_F32) hipLaunchKernelGGL(dw_kernel<P_F32>, grid, dim3(64), 0, ctx->stream, d);
     else if (prec == P_BF16) hipLaunchKernelGGL(dw_kernel<P_BF16>, grid, dim3(64), 0, ctx->stream, d);

@@ -36,7 +36,7 @@ struct WfEncArgs {
   const FieldDev *F;
   const int *ent_cnt;
   const float *qx, *qy, *qz;
-  void *feat;           // [level][slot]: uint32 (two 16-bit features) or float2 (FP32)
+  void *feat;           // [level][slot]: fg uint32 (pairs of 16-bit features) or fg float2
   int64_t n_slots;
   int n_entries;
   int kshift;           // entries hold at most 2^kshift queries (WF_SLOTS_LOG2: any count)
@@ -73,6 +73,7 @@ struct WfFieldArgs {
   float *acc_i;
   int64_t n_slots;
   int n_entries, n_cont;
+  int fg;               // feature groups of the field (1 or 4), host-side dispatch
 };
 
 struct WfResolveArgs {
@@ -104,7 +105,7 @@ hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes
 std::vector<std::pair<int, int>> wf_level_groups(const pfn_context *ctx, int slot,
                                                  const FieldDev &fd_host, size_t feat_bytes);
 // Field-kernel workgroups that are resident on the device at once.
-int wf_field_blocks(int prec, int mlp_bytes);
+int wf_field_blocks(int prec, int mlp_bytes, int fg = 1);
 // The encoding launches (one per level group), the direction encoding and the field kernel of
 // one round, on stream st.
 // split_levels: each group launch runs one thread per (level, query) instead of one per query.

@@ -243,12 +243,41 @@ __device__ __forceinline__ void store_feat(void *feat, int64_t i, float2 v) {
 }
 
 template <int P>
+__device__ __forceinline__ uint32_t pack_pair(float a, float b) {
+  if constexpr (P == P_F16) {
+    __half2 h = __floats2half2_rn(a, b);
+    return *reinterpret_cast<uint32_t *>(&h);
+  } else {
+    __bf16 lo = (__bf16)a, hi = (__bf16)b;
+    return (uint32_t)__builtin_bit_cast(unsigned short, lo) |
+           ((uint32_t)__builtin_bit_cast(unsigned short, hi) << 16);
+  }
+}
+
+// 8 features of one level: 16 bytes (16-bit) or 32 bytes (FP32) at element i.
+template <int P>
+__device__ __forceinline__ void store_feat8(void *feat, int64_t i, const float v[8]) {
+  if constexpr (P == P_F32) {
+    float4 *d = reinterpret_cast<float4 *>(feat) + 2 * i;
+    d[0] = make_float4(v[0], v[1], v[2], v[3]);
+    d[1] = make_float4(v[4], v[5], v[6], v[7]);
+  } else {
+    uint4 w;
+    w.x = pack_pair<P>(v[0], v[1]);
+    w.y = pack_pair<P>(v[2], v[3]);
+    w.z = pack_pair<P>(v[4], v[5]);
+    w.w = pack_pair<P>(v[6], v[7]);
+    reinterpret_cast<uint4 *>(feat)[i] = w;
+  }
+}
+
+template <int P>
 __device__ __forceinline__ float2 load_feat2(const void *feat, int64_t i) {
   if constexpr (P == P_F32) return reinterpret_cast<const float2 *>(feat)[i];
   else return load_feat<P>(reinterpret_cast<const uint32_t *>(feat) + i, 0u);
 }
 
-template <int P>
+template <int P, int FG>
 __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   // thread g: query c of entry t, over the first 2^kshift query indices of every entry (and,
   // with per_level, one level of it)
@@ -281,6 +310,24 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
   const int64_t s = wf_slot(t, c);
   const FieldDev &F = *e.F;
   const f3 x = clamp01(f3{e.qx[s], e.qy[s], e.qz[s]});
+  if constexpr (FG != 1) {
+    // 8 features per level: one 16- (or 32-) byte read per corner and one store per level
+    float v[8];
+    if (e.paired) {
+      encode_pos_level8<P>(F, l0, x, v);
+      store_feat8<P>(e.feat, (int64_t)l0 * e.n_slots + s, v);
+      if (l1 >= 8) {
+        encode_pos_level8<P>(F, l1, x, v);
+        store_feat8<P>(e.feat, (int64_t)l1 * e.n_slots + s, v);
+      }
+      return;
+    }
+    for (int lv = l0; lv < l1; ++lv) {
+      encode_pos_level8<P>(F, lv, x, v);
+      store_feat8<P>(e.feat, (int64_t)lv * e.n_slots + s, v);
+    }
+    return;
+  }
   if (e.paired) {
     // both levels' corner reads are issued before either store
     const bool two = l1 >= 8;
@@ -294,13 +341,21 @@ __global__ __launch_bounds__(WF_THREADS) void wf_encode_kernel(WfEncArgs e) {
     store_feat<P>(e.feat, (int64_t)lv * e.n_slots + s, encode_pos_level<P>(F, lv, x));
 }
 
-template <int P>
+template <int P, int FG>
 __global__ __launch_bounds__(WF_THREADS) void wf_dir_kernel(WfDirArgs e) {
   const int t = (int)(blockIdx.x * WF_THREADS + threadIdx.x);
   if (t >= e.n_entries) return;
   if (e.ent_cnt[t] == 0) return;
   const FieldDev &F = *e.F;
   const float2 u = e.ent_u[t];
+  if constexpr (FG != 1) {
+    float v[8];
+    for (int lv = 0; lv < F.levels; ++lv) {
+      encode_dir_level8<P>(F, lv, u.x, u.y, v);
+      store_feat8<P>(e.dfeat, (int64_t)lv * e.n_entries + t, v);
+    }
+    return;
+  }
   for (int lv = 0; lv < F.levels; ++lv)
     store_feat<P>(e.dfeat, (int64_t)lv * e.n_entries + t,
                   encode_dir_level<P>(F, lv, u.x, u.y));
@@ -436,6 +491,156 @@ void wf_field_kernel(WfFieldArgs a) {
     }
     // continuing rays carry the sum to the next round; ended rays (also those without a query
     // this round) store it
+    if (q == 0 && next != -2) {
+      float *dst = next >= 0 ? a.out_ci + 3 * (size_t)next : a.acc_i + 3 * (size_t)r;
+      dst[0] = ci.x + S.x;
+      dst[1] = ci.y + S.y;
+      dst[2] = ci.z + S.z;
+    }
+  }
+}
+
+// The field kernel for 8 features per level (4 feature groups): the same tiles and sums as
+// wf_field_kernel; a lane loads 16 (FP32: 32) bytes per level and query, and word g of level
+// 4q+j goes to word j of feature group g's operand.  Its larger weight image sets its occupancy.
+template <int P>
+__global__ __launch_bounds__(WF_THREADS) void wf_field8_kernel(WfFieldArgs a) {
+  extern __shared__ __align__(16) unsigned char lds_w[];
+  stage_weights(lds_w, a.mlp, a.mlp_bytes);
+  __syncthreads();
+  constexpr int FG = 4;
+  const FieldDev &F = *a.F;
+  const int lane = lane_id(), q = lane >> 4, col = lane & 15;
+  const int waves = (int)gridDim.x * (WF_THREADS / 64);
+  const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (WF_THREADS / 64) +
+                                                (int)(threadIdx.x >> 6));
+  const int n_tiles = (a.n_entries + 15) >> 4;
+  for (int rt = w0; rt < n_tiles; rt += waves) {
+    const int t = rt * 16 + col;
+    const bool tv = t < a.n_entries;
+    const int cnt = tv ? a.ent_cnt[t] : 0;
+    const int next = tv ? a.ent_next[t] : -2;
+    int kmax = cnt;
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) kmax = max(kmax, __shfl_xor(kmax, o));
+    kmax = __builtin_amdgcn_readfirstlane(kmax);
+    uint32_t r = 0;
+    f3 ci = {0.f, 0.f, 0.f};
+    if (next != -2) {
+      r = a.ent_ray[t];
+      if (t < a.n_cont)
+        ci = {a.in_ci[3 * (size_t)t], a.in_ci[3 * (size_t)t + 1], a.in_ci[3 * (size_t)t + 2]};
+    }
+    float gin = 0.0f;
+    if (cnt > 0 && q == 0) gin = a.jobs[find_job_ray(a.jobs, a.n_jobs, (int64_t)r)].g;
+    f3 S = {0.f, 0.f, 0.f};
+    if constexpr (P == P_F32) {
+      const float4 *df4 = reinterpret_cast<const float4 *>(a.dfeat);
+      const float4 *pf4 = reinterpret_cast<const float4 *>(a.feat);
+      float dir[FG][8];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+        const int lv = 4 * q + j;
+        if (cnt > 0 && lv < F.levels) {
+          const int64_t i = (int64_t)lv * a.n_entries + t;
+          lo = df4[2 * i];
+          hi = df4[2 * i + 1];
+        }
+        const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+        for (int g = 0; g < FG; ++g) {
+          dir[g][2 * j] = v[2 * g];
+          dir[g][2 * j + 1] = v[2 * g + 1];
+        }
+      }
+      for (int k = 0; k < kmax; ++k) {
+        const bool valid = k < cnt;
+        const int64_t sl = wf_slot(t, k);
+        float pos[FG][8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          float4 lo = make_float4(0.f, 0.f, 0.f, 0.f), hi = lo;
+          const int lv = 4 * q + j;
+          if (valid && lv < F.levels) {
+            const int64_t i = (int64_t)lv * a.n_slots + sl;
+            lo = pf4[2 * i];
+            hi = pf4[2 * i + 1];
+          }
+          const float v[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+          for (int g = 0; g < FG; ++g) {
+            pos[g][2 * j] = v[2 * g];
+            pos[g][2 * j + 1] = v[2 * g + 1];
+          }
+        }
+        f3 W = {0.f, 0.f, 0.f};
+        if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
+        const f32x4 out = mlp_forward16_f32_g<FG>(reinterpret_cast<const float *>(lds_w),
+                                                  F.hidden, pos, dir, gin);
+        if (q == 0 && valid) {
+          S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+          S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+          S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+        }
+      }
+    } else {
+      typedef Mma<P> M;
+      typedef typename M::vec vec;
+      typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+      const uint4 *fw = reinterpret_cast<const uint4 *>(a.feat);
+      const uint4 *dfw = reinterpret_cast<const uint4 *>(a.dfeat);
+      u32x4 dwg[FG];
+#pragma unroll
+      for (int g = 0; g < FG; ++g) dwg[g] = u32x4{0u, 0u, 0u, 0u};
+      if (cnt > 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (4 * q + j < F.levels) {
+            const uint4 w4 = dfw[(int64_t)(4 * q + j) * a.n_entries + t];
+            dwg[0][j] = w4.x;
+            dwg[1][j] = w4.y;
+            dwg[2][j] = w4.z;
+            dwg[3][j] = w4.w;
+          }
+      }
+      vec b1[FG];
+#pragma unroll
+      for (int g = 0; g < FG; ++g) b1[g] = __builtin_bit_cast(vec, dwg[g]);
+      float gz[8] = {gin, 0, 0, 0, 0, 0, 0, 0};
+      const vec *w = reinterpret_cast<const vec *>(lds_w);
+      f32x4 pre[4];
+      mlp_input16_g<P, FG>(w, b1, M::pack(gz), pre);
+      for (int k = 0; k < kmax; ++k) {
+        const bool valid = k < cnt;
+        const int64_t sl = wf_slot(t, k);
+        u32x4 pwg[FG];
+#pragma unroll
+        for (int g = 0; g < FG; ++g) pwg[g] = u32x4{0u, 0u, 0u, 0u};
+        if (valid) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (4 * q + j < F.levels) {
+              const uint4 w4 = fw[(int64_t)(4 * q + j) * a.n_slots + sl];
+              pwg[0][j] = w4.x;
+              pwg[1][j] = w4.y;
+              pwg[2][j] = w4.z;
+              pwg[3][j] = w4.w;
+            }
+        }
+        vec b0[FG];
+#pragma unroll
+        for (int g = 0; g < FG; ++g) b0[g] = __builtin_bit_cast(vec, pwg[g]);
+        f3 W = {0.f, 0.f, 0.f};
+        if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
+        const f32x4 out = mlp_rest16_g<P, FG>(w, F.hidden, b0, pre);
+        if (q == 0 && valid) {
+          S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+          S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+          S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+        }
+      }
+    }
     if (q == 0 && next != -2) {
       float *dst = next >= 0 ? a.out_ci + 3 * (size_t)next : a.acc_i + 3 * (size_t)r;
       dst[0] = ci.x + S.x;
@@ -583,7 +788,7 @@ static void launch_k1(const WfArgs &a, int blocks, hipStream_t st) {
   hipLaunchKernelGGL((wf_march_kernel<VT, DIRECT>), dim3(blocks), dim3(WF_THREADS), 0, st, a);
 }
 
-template <int P>
+template <int P, int FG>
 static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &e,
                              const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
                              const WfFieldArgs &f, int field_blocks, bool split_levels,
@@ -593,7 +798,7 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
   {
     hipStream_t ds = fst ? fst : st;
     const int ts = timing_begin_on(ctx, ds);
-    hipLaunchKernelGGL((wf_dir_kernel<P>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
+    hipLaunchKernelGGL((wf_dir_kernel<P, FG>), dim3((dg.n_entries + WF_THREADS - 1) / WF_THREADS),
                        dim3(WF_THREADS), 0, ds, dg);
     timing_end_on(ctx, ts, TK_WF_DIR, ds);
   }
@@ -620,7 +825,7 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
       eb = 8 * ((eb + per - 1) / per);
     }
     const int ts = timing_begin_on(ctx, st);
-    hipLaunchKernelGGL((wf_encode_kernel<P>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
+    hipLaunchKernelGGL((wf_encode_kernel<P, FG>), dim3(eb), dim3(WF_THREADS), 0, st, ee);
     timing_end_on(ctx, ts, TK_WF_ENCODE, st);
   }
   if (fst) {
@@ -630,8 +835,12 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
     st = fst;
   }
   const int ts = timing_begin_on(ctx, st);
-  hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
-                     (size_t)f.mlp_bytes, st, f);
+  if constexpr (FG == 1)
+    hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
+                       (size_t)f.mlp_bytes, st, f);
+  else
+    hipLaunchKernelGGL((wf_field8_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
+                       (size_t)f.mlp_bytes, st, f);
   timing_end_on(ctx, ts, TK_WF_FIELD, st);
   return hipSuccess;
 }
@@ -640,23 +849,35 @@ hipError_t wf_launch_field_pass(pfn_context *ctx, hipStream_t st, int prec, cons
                                 const WfDirArgs &dg, const std::vector<std::pair<int, int>> &groups,
                                 const WfFieldArgs &f, int field_blocks, bool split_levels,
                                 hipStream_t field_st, hipEvent_t enc_done) {
+  if (f.fg != 1) {
+    if (prec == P_F32)
+      return launch_k23<P_F32, 4>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                                  enc_done);
+    if (prec == P_BF16)
+      return launch_k23<P_BF16, 4>(ctx, st, e, dg, groups, f, field_blocks, split_levels,
+                                   field_st, enc_done);
+    return launch_k23<P_F16, 4>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                                enc_done);
+  }
   if (prec == P_F32)
-    return launch_k23<P_F32>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
-                             enc_done);
+    return launch_k23<P_F32, 1>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                                enc_done);
   if (prec == P_BF16)
-    return launch_k23<P_BF16>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+    return launch_k23<P_BF16, 1>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
+                                 enc_done);
+  return launch_k23<P_F16, 1>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
                               enc_done);
-  return launch_k23<P_F16>(ctx, st, e, dg, groups, f, field_blocks, split_levels, field_st,
-                           enc_done);
 }
 
 template <int P>
-static int field_blocks_resident(int mlp_bytes) {
+static int field_blocks_resident(int mlp_bytes, int fg) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field_kernel<P>, WF_THREADS,
-                                                   (size_t)mlp_bytes) != hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
+  const hipError_t e =
+      fg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field_kernel<P>,
+                                                             WF_THREADS, (size_t)mlp_bytes)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field8_kernel<P>,
+                                                             WF_THREADS, (size_t)mlp_bytes);
+  if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int cus = 256;
   int dev = 0;
   if (hipGetDevice(&dev) == hipSuccess)
@@ -664,10 +885,10 @@ static int field_blocks_resident(int mlp_bytes) {
   return per_cu * cus;
 }
 
-int wf_field_blocks(int prec, int mlp_bytes) {
-  return prec == P_F32    ? field_blocks_resident<P_F32>(mlp_bytes)
-         : prec == P_BF16 ? field_blocks_resident<P_BF16>(mlp_bytes)
-                          : field_blocks_resident<P_F16>(mlp_bytes);
+int wf_field_blocks(int prec, int mlp_bytes, int fg) {
+  return prec == P_F32    ? field_blocks_resident<P_F32>(mlp_bytes, fg)
+         : prec == P_BF16 ? field_blocks_resident<P_BF16>(mlp_bytes, fg)
+                          : field_blocks_resident<P_F16>(mlp_bytes, fg);
 }
 
 std::vector<std::pair<int, int>> wf_level_groups(const pfn_context *ctx, int slot,
@@ -725,8 +946,10 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   pix_begin[mj.size()] = pixels;
   if (rays >= (int64_t)1 << 31)
     return pfn_fail(ctx, PFN_ERR_UNSUPPORTED, "wavefront render: more than 2^31 ray samples");
-  const size_t entries = (size_t)std::min<int64_t>(rays, WF_MAX_ENTRIES);
-  const size_t fbytes = prec == P_F32 ? 8 : 4;
+  // rounds of fewer rays for wider features, so that the feature buffers keep their size
+  const int fg = fd_host.fg;
+  const size_t entries = (size_t)std::min<int64_t>(rays, WF_MAX_ENTRIES / fg);
+  const size_t fbytes = (prec == P_F32 ? 8 : 4) * (size_t)fg;
   PFN_HIP(ctx, wf_reserve(w, entries, (size_t)rays, fbytes));
   if (w.pix_cap < mj.size() + 1) {
     free_p(w.pix_begin);
@@ -768,7 +991,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
       }
     }
   }
-  const int fb_max = wf_field_blocks(prec, m.mlp_bytes);
+  const int fb_max = wf_field_blocks(prec, m.mlp_bytes, fg);
   // march kernels on sa, encodings on sb, field kernels on sc
   hipStream_t sa = ctx->stream, sb = overlap ? w.side : ctx->stream,
               sc = overlap ? w.side2 : ctx->stream;
@@ -857,6 +1080,7 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
     f.n_slots = e.n_slots;
     f.n_entries = n_in;
     f.n_cont = n_cont;
+    f.fg = fg;
     f.in_ci = w.list_ci[cur];
     f.out_ci = w.list_ci[cur ^ 1];
     const int fb = std::max(1, std::min((n_in + 63) / 64, fb_max));

@@ -52,17 +52,35 @@ def fctx():
     return gpu_context(vol, tf, lights)
 
 
-@pytest.mark.parametrize("levels,hidden,log2_table", [(16, 3, 19), (16, 1, 12), (7, 2, 10)])
-def test_field_query_parity_all_precisions(orc, fctx, levels, hidden, log2_table):
+# (levels, hidden layers, log2 table size, features per level, growth): the configuration's
+# field, small ones, and the paper's encoding (8 features per level; 16 levels at growth 2 reach
+# 16 * 2^15 cells per axis)
+QUERY_CASES = [(16, 3, 19, 2, 1.5), (16, 1, 12, 2, 1.5), (7, 2, 10, 2, 1.5),
+               (16, 3, 19, 8, 1.5), (16, 5, 14, 8, 2.0), (6, 2, 10, 8, 1.5)]
+
+
+@pytest.mark.parametrize("levels,hidden,log2_table,feats,growth", QUERY_CASES)
+def test_field_query_parity_all_precisions(orc, fctx, levels, hidden, log2_table, feats, growth):
     import torch
     from paper_2304_07338_amd.pfn import FieldConfig
-    cfg = FieldConfig(**dict(C1_FIELD, levels=levels, hidden_layers=hidden, log2_table=log2_table))
+    cfg = FieldConfig(**dict(C1_FIELD, levels=levels, hidden_layers=hidden, log2_table=log2_table,
+                             feats_per_level=feats, growth=growth))
     desc = oracle_desc(orc, cfg)
-    say(f"field query parity levels={levels} hidden={hidden} T=2^{log2_table}")
+    say(f"field query parity levels={levels} hidden={hidden} T=2^{log2_table} F={feats} "
+        f"growth={growth}")
     fctx.field_select(1)
     fctx.field_init(cfg, seed=3)
     assert fctx.field_num_params() == orc.field_num_params(desc)
     p = random_params(orc, desc, seed=levels + hidden)
+    if growth == 2.0:
+        # direction levels finer than 4096 cells (up to 16 * 2^15) turn the FP32 direction
+        # coordinates' 8 ulps into fractions of a cell, and the per-query allowance below would
+        # swamp everything else: their features are zero here (position levels keep theirs)
+        L = orc.field_layout(desc)
+        for lv in range(levels):
+            if L.dir_res[lv] > 4096:
+                a0 = L.pos_params + feats * L.dir_off[lv]
+                p[a0:a0 + feats * (L.dir_off[lv + 1] - L.dir_off[lv])] = 0.0
     fctx.field_set_params(torch.tensor(p, device="cuda:0"))
     fctx.field_set_kappa(2e-3)
     n = 16 * 61 + 5  # several waves and a ragged tail
@@ -82,8 +100,11 @@ def test_field_query_parity_all_precisions(orc, fctx, levels, hidden, log2_table
     say("  f32 max|dL'|", d.max(), "rms", np.sqrt((d ** 2).mean()), "|ref| rms",
         np.sqrt((ref ** 2).mean()), "max d/bar", (d / bar).max(), "median sens", np.median(sens))
     assert np.all(d <= bar)
-    dec = 2e-3 * 10.0 ** (-5.0 * ref)
-    assert rel_rmse(rgb.cpu().numpy(), dec) <= 1e-4
+    # the decoded radiance of the same queries is kappa 10^(-psi L') of the GPU's own L' (its
+    # difference from the oracle's L' is bounded above), up to the FP32 exponential
+    lpg = lp.cpu().numpy().astype(np.float64)
+    dec = np.vectorize(lambda v: 2e-3 * orc.exp_decode(v, 5.0))(lpg)
+    assert rel_rmse(rgb.cpu().numpy(), dec) <= 1e-5
     # 16-bit paths against the oracle with parameters rounded the same way
     # bars: about 10x the largest measured over the three fields (f16 RMS 1.6e-5, max 6.9e-5;
     # bf16 RMS 1.2e-4, max 4.7e-4), which come from activations that the GPU and the oracle
@@ -92,11 +113,13 @@ def test_field_query_parity_all_precisions(orc, fctx, levels, hidden, log2_table
         lp = fctx.field_query(dx, dw, dg, precision=prec, decode=False)
         fctx.sync()
         ref = orc.field_forward(desc, pd, x, w, g, rounding=rounding)
-        d = lp.cpu().numpy() - ref
+        # the 16-bit paths take the same FP32 direction coordinates: what exceeds the per-query
+        # coordinate allowance of the FP32 check is held to the bars
+        d = np.maximum(np.abs(lp.cpu().numpy() - ref) - 2.0 * sens, 0.0)
         rms = float(np.sqrt(np.mean(d ** 2)))
-        say(f"  {prec} rms|dL'|", rms, "max", np.abs(d).max())
+        say(f"  {prec} rms excess|dL'|", rms, "max", d.max())
         assert rms <= tol_rms
-        assert np.abs(d).max() <= tol_max
+        assert d.max() <= tol_max
 
 
 def test_field_query_empty_and_tiny(orc, fctx):
@@ -147,3 +170,47 @@ def test_render_with_field_parity(orc, strategy):
                                                             g=0.3),
                                 field=(desc, p.astype(np.float64), rounding, 5e-3))
         check_err(img.cpu().numpy().reshape(-1, 3), ref, tol, tol_max, prec)
+
+
+def test_render_with_wide_field(orc):
+    """A field of 8 features per level (the paper's encoding) lights the wavefront form of the
+    ray marcher (FP32 and FP16 against the oracle); the fused kernel refuses it."""
+    import torch
+    from paper_2304_07338_amd import scenegen as sg
+    from paper_2304_07338_amd.pfn import FieldConfig, PfnError, RenderConfig, INDIRECT_FIELD
+    say("render with an 8-feature field, stride 4, 24x20 (wavefront)")
+    w, vol, tf, lights = scene_arrays("c0")
+    ctx = gpu_context(vol, tf, lights)
+    ctx.set_render_strategy("wavefront")
+    cfg = FieldConfig(**dict(C1_FIELD, feats_per_level=8, log2_table=16))
+    desc = oracle_desc(orc, cfg)
+    ctx.field_select(0)
+    ctx.field_init(cfg, seed=0)
+    p = random_params(orc, desc, seed=12, out_scale=0.2)
+    ctx.field_set_params(torch.tensor(p, device="cuda:0"))
+    ctx.field_set_kappa(5e-3)
+    cam = sg.make_camera(w.seed, 4, 24, 20)
+    os_ = oracle_scene(orc, vol, tf, lights)
+    for prec, rounding, tol, tol_max in (("f32", 0, 1e-4, 5e-5), ("f16", 1, 3e-4, 2e-4)):
+        img = ctx.render_frame(cam, RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3,
+                                                 field_precision=prec))
+        ctx.sync()
+        ref = orc.render_pixels(os_, cam, orc.render_params(indirect=orc.IND_FIELD, field_stride=4,
+                                                            g=0.3),
+                                field=(desc, p.astype(np.float64), rounding, 5e-3))
+        check_err(img.cpu().numpy().reshape(-1, 3), ref, tol, tol_max, f"8 features, {prec}")
+    img16 = img.clone()
+    ctx.set_render_strategy("fused")
+    with pytest.raises(PfnError) as e:
+        ctx.render_frame(cam, RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3))
+    assert e.value.status == -5
+    # the autotuner times the wavefront form only, and graph replay leaves it in place
+    ctx.set_render_strategy("auto")
+    ctx.set_launch_mode(0, use_graph=True)
+    rc = RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3, field_precision="f16")
+    best = ctx.autotune_batch([cam], [rc], iters=1)
+    assert best["strategy"] == "wavefront"
+    img = ctx.render_frame(cam, rc)
+    ctx.sync()
+    torch.testing.assert_close(img, img16, rtol=1e-5, atol=1e-9)
+    ctx.close()

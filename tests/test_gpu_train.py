@@ -142,27 +142,38 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-@pytest.mark.parametrize("levels,hidden,log2_table", [(16, 3, 12), (8, 2, 12), (16, 1, 12),
-                                                     (16, 3, 19)])
-def test_forward_backward_gradients(orc, tctx, levels, hidden, log2_table):
+@pytest.mark.parametrize("levels,hidden,log2_table,feats,growth",
+                         [(16, 3, 12, 2, 1.5), (8, 2, 12, 2, 1.5), (16, 1, 12, 2, 1.5),
+                          (16, 3, 19, 2, 1.5), (16, 3, 14, 8, 1.5), (16, 5, 16, 8, 2.0)])
+def test_forward_backward_gradients(orc, tctx, levels, hidden, log2_table, feats, growth):
     """Loss and gradient of every grid level and weight matrix against the oracle.  With
     T = 2^19 (the benchmark's table) position levels 0-3 and direction levels 0-9 are dense, so
-    both scatter branches are compared level by level."""
+    both scatter branches are compared level by level; the paper's encoding (8 features per
+    level, 16 levels at growth 2) is compared the same way."""
     import torch
     from paper_2304_07338_amd.pfn import FieldConfig
     ctx, _ = tctx
-    cfg = FieldConfig(levels=levels, hidden_layers=hidden, log2_table=log2_table)
+    cfg = FieldConfig(levels=levels, hidden_layers=hidden, log2_table=log2_table,
+                      feats_per_level=feats, growth=growth)
     desc = odesc(orc, cfg)
     ctx.field_select(1)
     ctx.field_init(cfg, seed=1)
     p, L = _random_params(orc, desc, seed=levels * 10 + hidden)
+    if growth == 2.0:
+        # direction levels finer than 4096 cells: the FP32 direction coordinates (8 ulps) move
+        # their fractions by up to 0.25 of a cell at 16 * 2^15 cells, which would flip ReLUs in
+        # every sample; their features are set to zero (their gradients are still compared)
+        for l in range(levels):
+            if L.dir_res[l] > 4096:
+                a0 = L.pos_params + feats * L.dir_off[l]
+                p[a0:a0 + feats * (L.dir_off[l + 1] - L.dir_off[l])] = 0.0
     ctx.field_set_params(torch.tensor(p, device="cuda:0"))
     n = 16 * 40 + 7
     pd = p.astype(np.float64)
     x, w, g = _relu_safe_samples(orc, desc, L, pd, n, seed=3)
     tgt = np.random.default_rng(13).uniform(0, 1, (n, 3)).astype(np.float32)
     dev = [torch.tensor(a, device="cuda:0") for a in (x, w, g, tgt)]
-    segs = _segments(L)
+    segs = _segments(L, feats)
     if log2_table == 19 and levels == 16:
         assert [k for k in segs if k.startswith("pos") and k.endswith("d")] == \
             ["pos0d", "pos1d", "pos2d", "pos3d"]
@@ -255,12 +266,13 @@ def test_adam_step_matches_oracle(orc, tctx):
     assert err <= 3e-7 * max(1.0, np.abs(p).max())  # measured 3e-8
 
 
-def test_training_fits_a_smooth_target(orc, tctx):
+@pytest.mark.parametrize("feats", [2, 8])
+def test_training_fits_a_smooth_target(orc, tctx, feats):
     from paper_2304_07338_amd.pfn import FieldConfig, TrainConfig
     ctx, cache = tctx
     ctx.field_select(3)
-    ctx.field_init(FieldConfig(log2_table=14), seed=3)
-    say("train 600 steps at 2^14 on a smooth 3-bin cache")
+    ctx.field_init(FieldConfig(log2_table=14, feats_per_level=feats), seed=3)
+    say(f"train 600 steps at 2^14 on a smooth 3-bin cache, {feats} features per level")
     hist = ctx.train_field(TrainConfig(steps=600, log2_batch=14, decay_start=420, seed=11))
     say("  loss", hist[0], "->", hist[-10:].mean())
     assert np.all(np.isfinite(hist))
