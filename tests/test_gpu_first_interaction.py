@@ -82,14 +82,17 @@ def test_direct_only_ragged_three_samples_and_light_mask(orc, fi):
         _agree(img.cpu().numpy(), ref, 2e-5, f"direct only, 3 spp, mask {mask}")
 
 
+@pytest.mark.parametrize("feats", [2, 8])
 @pytest.mark.parametrize("prec,rounding,rtol", [("f32", 0, 1e-3), ("f16", 1, 2e-3)])
-def test_field_indirect_two_sample_groups(orc, fi, prec, rounding, rtol):
-    """20 samples per pixel: two groups of 16 (a full tile and a partial one)."""
+def test_field_indirect_two_sample_groups(orc, fi, prec, rounding, rtol, feats):
+    """20 samples per pixel: two groups of 16 (a full tile and a partial one); fields of 2 and
+    of 8 features per level (the paper's encoding)."""
     import torch
     from paper_2304_07338_amd.pfn import FieldConfig, INDIRECT_FIELD
     from test_gpu_field import C1_FIELD, oracle_desc, random_params
     ctx = fi["ctx"]
-    cfg = FieldConfig(**C1_FIELD)
+    cfg = FieldConfig(**dict(C1_FIELD, feats_per_level=feats,
+                             log2_table=C1_FIELD["log2_table"] if feats == 2 else 16))
     desc = oracle_desc(orc, cfg)
     ctx.field_select(0)
     ctx.field_init(cfg, seed=0)
@@ -102,7 +105,7 @@ def test_field_indirect_two_sample_groups(orc, fi, prec, rounding, rtol):
     ctx.sync()
     ref = orc.fi_pixels(fi["os"], cam, orc.fi_params(spp=20, g=0.3, indirect=orc.IND_FIELD, seed=8),
                         field=(desc, p.astype(np.float64), rounding, 5e-3))
-    _agree(img.cpu().numpy(), ref, rtol, f"field {prec}, 20 spp, 24x20")
+    _agree(img.cpu().numpy(), ref, rtol, f"field {prec}, {feats} features, 20 spp, 24x20")
 
 
 def test_frame_of_two_chunks_sampled_and_deterministic(orc, fi):
