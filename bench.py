@@ -734,16 +734,33 @@ def matched_rmse(args):
         """set the scene, rebuild every derived quantity and render the first frame"""
         torch.cuda.synchronize()
         ts = time.perf_counter()
+        marks = []
+
+        def mark(name):  # stage boundaries (a synchronisation each, microseconds)
+            torch.cuda.synchronize()
+            marks.append((name, time.perf_counter()))
+
         ctx.set_transfer_function(tf_table, w.extinction)
         ctx.set_lights(lights_arr)
         ctx.build_light_volume(0.5)
+        mark("light_volume")
         st = ctx.trace_photon_cache(1 << args.mr_photons, wl.C1_G_BINS, cache_res=128,
                                     seed=seed, max_collisions=8, rr_start=3)
+        mark("trace_and_cache")
         ctx.field_init(FieldConfig(), seed=seed)
         hist = ctx.train_field(TrainConfig(steps=args.train_steps, log2_batch=18, seed=seed))
+        mark("train")
         ctx.render_frame(cam, field_rc(0.4), out)
-        torch.cuda.synchronize()
-        return time.perf_counter() - ts, st, float(np.mean(hist[-20:]))
+        mark("first_frame")
+        prev, stages = ts, {}
+        for name, t in marks:
+            stages[name] = round(t - prev, 3)
+            prev = t
+        log(f"[mr] stages (s): {stages}")
+        stage_log.append(stages)
+        return marks[-1][1] - ts, st, float(np.mean(hist[-20:]))
+
+    stage_log = []
 
     lat0, st, loss = rebuild(tf, la, 11)
     log(f"[mr] initial build + first frame {lat0:.2f}s ({st['n_records']} records, loss {loss:.4g})")
@@ -833,6 +850,8 @@ def matched_rmse(args):
                    "train_steps": args.train_steps},
         "edit_to_first_frame_s": {"initial": round(lat0, 3), "transfer_function": round(lat_tf, 3),
                                   "light": round(lat_light, 3)},
+        "edit_stages_s": {"initial": stage_log[0], "transfer_function": stage_log[1],
+                          "light": stage_log[2]},
         "per_g": per_g,
     }
 

@@ -79,10 +79,14 @@ typedef struct {
 pfn_status pfn_set_lights(pfn_context *ctx, const pfn_point_light *host_lights, int n_lights);
 /* Light-transmittance grid for direct light (one channel per light) at half the volume
  * resolution per axis, each value the exact shadow-march transmittance from the grid point to
- * the light with `step_voxels` steps (global shadows, Section 4.3).  With at most 3 lights a
- * context-owned copy holding the four (x, y) corner texels of every cell (24 bytes per cell)
- * is also built, for the ray marcher's lookups. */
+ * the light with `step_voxels` steps (global shadows, Section 4.3).  With at most 3 lights and
+ * at most 2^24 texels a context-owned copy holding the four (x, y) corner texels of every cell
+ * (24 bytes per cell) is also built, for the ray marcher's lookups. */
 pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels);
+/* Copy the light-transmittance grid to dev_out: rx * ry * rz texels (r = (n + 1) / 2 of each
+ * volume side), x fastest, 4 binary16 values per texel (channel l = light l; unused channels
+ * 1).  n_texels must equal rx * ry * rz.  PFN_ERR_NOT_READY without a built grid. */
+pfn_status pfn_get_light_volume(pfn_context *ctx, uint16_t *dev_out, size_t n_texels);
 
 /* ------------------------------------------------------------------ 1. photon cache */
 typedef struct {

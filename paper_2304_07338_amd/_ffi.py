@@ -81,6 +81,7 @@ SIGNATURES = {
     "pfn_set_transfer_function": (C.c_int, [ctxp, C.POINTER(C.c_float), C.c_float]),
     "pfn_set_lights": (C.c_int, [ctxp, C.POINTER(PointLight), C.c_int]),
     "pfn_build_light_volume": (C.c_int, [ctxp, C.c_float]),
+    "pfn_get_light_volume": (C.c_int, [ctxp, vp, C.c_size_t]),
     "pfn_trace_photon_cache": (C.c_int, [ctxp, C.POINTER(TraceParams), C.POINTER(TraceStats)]),
     "pfn_get_records": (C.c_int, [ctxp, vp, vp, vp, vp, vp, C.c_uint64, C.POINTER(C.c_uint64)]),
     "pfn_get_cache": (C.c_int, [ctxp, vp, C.c_size_t]),

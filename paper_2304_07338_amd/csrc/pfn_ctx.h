@@ -234,6 +234,7 @@ hipError_t launch_light_quad(pfn_context *ctx);
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
                                int nz);
 hipError_t launch_light_volume(pfn_context *ctx, float step);
+hipError_t launch_light_unbrick(pfn_context *ctx, void *out);
 hipError_t launch_field_pack(pfn_context *ctx, FieldSlot &f, int prec);
 hipError_t launch_field_pack_mlp(pfn_context *ctx, FieldSlot &f, int prec);
 hipError_t launch_field_pack_bwd(pfn_context *ctx, FieldSlot &f, int prec);

@@ -54,13 +54,18 @@ hipError_t launch_quad_volume(pfn_context *ctx) {
 
 struct LightVolArgs {
   const void *vol;
-  BrickGrid vg, lvg;
+  const uint2 *qvol;  // quad copy of a binary16 volume, or NULL
+  BrickGrid vg, qg, lvg;
   const float4 *tf;
   float ext_scale, step;
   int n_lights;
   float lp[4][3];
   ushort4 *out;
 };
+
+// exp(-17.5) = 2.5e-8 is below half the smallest binary16 subnormal (2^-25 = 3.0e-8): a
+// transmittance at larger optical depth rounds to 0
+#define LV_TAU_ZERO 17.5f
 
 template <typename VT>
 __global__ void light_volume_kernel(LightVolArgs a) {
@@ -87,11 +92,14 @@ __global__ void light_volume_kernel(LightVolArgs a) {
     float tend = fminf(t1, dist);
     if (!(tend > t0)) continue;
     float len = tend - t0, tau = 0.0f;
-    for (int k = 0;; ++k) {
+    // tau only grows (non-negative terms); past LV_TAU_ZERO the binary16 result is 0 whatever
+    // the rest of the march adds, so the march stops there with the same output
+    for (int k = 0; tau <= LV_TAU_ZERO; ++k) {
       float l_ = fminf(a.step, len - (float)k * a.step);
       if (!(l_ > 0.0f)) break;
       float t = t0 + (float)k * a.step + 0.5f * l_;
-      float rho = density_at(reinterpret_cast<const VT *>(a.vol), a.vg, x + d * t);
+      float rho = density_march(reinterpret_cast<const VT *>(a.vol), a.vg, a.qvol, a.qg,
+                                x + d * t);
       tau = fmaf(tf_lookup(tf, rho).w * a.ext_scale, l_, tau);
     }
     T[l] = expf(-tau);
@@ -107,7 +115,9 @@ __global__ void light_volume_kernel(LightVolArgs a) {
 hipError_t launch_light_volume(pfn_context *ctx, float step) {
   LightVolArgs a{};
   a.vol = ctx->vol;
+  a.qvol = ctx->qvol;
   a.vg = ctx->vol_grid;
+  a.qg = ctx->qvol_grid;
   a.lvg = ctx->lv_grid;
   a.tf = ctx->tf_dev;
   a.ext_scale = ctx->ext_scale;
@@ -122,6 +132,26 @@ hipError_t launch_light_volume(pfn_context *ctx, float step) {
     hipLaunchKernelGGL(light_volume_kernel<__half>, dim3(blocks), dim3(256), 0, ctx->stream, a);
   else
     hipLaunchKernelGGL(light_volume_kernel<float>, dim3(blocks), dim3(256), 0, ctx->stream, a);
+  return hipGetLastError();
+}
+
+// The light grid in plain x-fastest order (4 binary16 values per texel).
+__global__ void light_unbrick_kernel(const ushort4 *__restrict__ lv, BrickGrid g,
+                                     ushort4 *__restrict__ out) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)g.nx * g.ny * g.nz;
+  if (i >= n) return;
+  const int x = (int)(i % g.nx);
+  const int y = (int)((i / g.nx) % g.ny);
+  const int z = (int)(i / ((size_t)g.nx * g.ny));
+  out[i] = lv[brick_ox(x) + brick_oy(g, y) + brick_oz(g, z)];
+}
+
+hipError_t launch_light_unbrick(pfn_context *ctx, void *out) {
+  const BrickGrid &g = ctx->lv_grid;
+  size_t n = (size_t)g.nx * g.ny * g.nz;
+  hipLaunchKernelGGL(light_unbrick_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     ctx->stream, ctx->lightvol, g, reinterpret_cast<ushort4 *>(out));
   return hipGetLastError();
 }
 

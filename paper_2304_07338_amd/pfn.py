@@ -190,6 +190,7 @@ class Context:
         dt = {torch.float32: PFN_F32, torch.float16: PFN_F16}[density.dtype]
         nz, ny, nx = density.shape
         self._ok(self.lib.pfn_set_volume(self.h, _ptr(density), dt, nx, ny, nz))
+        self._vol_shape = (nz, ny, nx)
 
     def set_transfer_function(self, table: np.ndarray, extinction_scale: float):
         t = np.ascontiguousarray(table, dtype=np.float32).reshape(256 * 4)
@@ -209,6 +210,14 @@ class Context:
 
     def build_light_volume(self, step_voxels: float = 0.5):
         self._ok(self.lib.pfn_build_light_volume(self.h, step_voxels))
+
+    def get_light_volume(self):
+        """The light-transmittance grid as float16 [rz][ry][rx][4] (channel = light)."""
+        import torch
+        rz, ry, rx = ((n + 1) // 2 for n in self._vol_shape)
+        out = torch.empty((rz, ry, rx, 4), dtype=torch.float16, device=f"cuda:{self.device}")
+        self._ok(self.lib.pfn_get_light_volume(self.h, _ptr(out), rx * ry * rz))
+        return out
 
     # ------------------------------------------------------------------ photon cache
     def trace_photon_cache(self, n_photons: int, g_bins: Sequence[float], cache_res: int,
