@@ -202,9 +202,9 @@ void orc_pt_pixels(const orc_scene *s, const orc_camera *c, int spp, int max_bou
  * albedo a(x): L_d = sum_l I_l p_g(mu_l) V_l / r_l^2 with V_l in {0, 1} from a delta-tracking
  * walk toward light l, and L_i from the photon field (Eq. 2, decoded with Eq. 7) or the photon
  * cache.  The sample contributes a(x) * (L_d + L_i); the pixel is the mean over its spp samples.
- * Random numbers: the walk of sample s of pixel p uses Philox item p*spp + s of stream 10;
- * the visibility walks of the k-th collision among samples 16j .. 16j+15 of pixel p use item
- * p*spp + 16j + k of stream 11 (lights in order, one stream). */
+ * Random numbers: the walk of sample s of pixel p uses Philox item p*spp + s of stream 10,
+ * and the visibility walks from its collision item p*spp + s of stream 11 (lights in order,
+ * one stream). */
 typedef struct {
   int spp;
   double g;

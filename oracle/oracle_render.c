@@ -317,9 +317,7 @@ static void fi_one(const orc_scene *s, const orc_camera *cam, const orc_fi_param
   memset(&ip, 0, sizeof(ip));
   ip.g = p->g;
   ip.indirect = p->indirect;
-  int k = 0; /* collisions so far among the samples of the current group of 16 */
   for (int smp = 0; smp < p->spp; ++smp) {
-    if (smp % 16 == 0) k = 0;
     int ok = 0;
     double x[3] = {0, 0, 0}, alb[3] = {0, 0, 0}, Ld[3] = {0, 0, 0}, Li[3] = {0, 0, 0};
     if (hit) {
@@ -335,8 +333,7 @@ static void fi_one(const orc_scene *s, const orc_camera *cam, const orc_fi_param
         orc_transfer(s, orc_density(s, x), &sig, alb);
         /* Direct illumination: next-event estimation, visibility by delta tracking */
         orc_rng vr;
-        orc_rng_init(&vr, p->seed,
-                     (uint64_t)pix * (uint64_t)p->spp + (uint64_t)(16 * (smp / 16) + k),
+        orc_rng_init(&vr, p->seed, (uint64_t)pix * (uint64_t)p->spp + (uint64_t)smp,
                      ORC_STREAM_FI_NEE);
         for (int l = 0; l < s->n_lights; ++l) {
           if (!light_on(p->light_mask, l)) continue;
@@ -354,7 +351,6 @@ static void fi_one(const orc_scene *s, const orc_camera *cam, const orc_fi_param
         }
         /* Photon field prediction and decoding (or the cache) at the interaction */
         indirect_light(&ip, cache, field, x, wo, Li);
-        ++k;
       }
     }
     const int64_t j = (int64_t)smp;

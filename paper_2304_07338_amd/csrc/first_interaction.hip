@@ -24,12 +24,13 @@
 // sampling).
 //
 // Random numbers: the walk of sample s of pixel p uses Philox item p * spp + s of stream
-// STREAM_FI_SAMPLE; the visibility walks of the k-th collision among samples 16j .. 16j+15 use
-// item p * spp + 16j + k of stream STREAM_FI_NEE.  Per-ray results do not depend on the entry a
-// ray gets, so frames are deterministic.
+// STREAM_FI_SAMPLE, and the visibility walks from its collision item p * spp + s of stream
+// STREAM_FI_NEE (an entry keeps the mask of its group's samples that collided, so the k-th
+// collision is known to be that of the k-th set bit).  Per-ray results do not depend on the
+// entry a ray gets, so frames are deterministic.
 #include "wavefront.h"
 
-#define FI_GROUP 16  // samples of a pixel per ray of the layout (fixes the NEE random numbers)
+#define FI_GROUP 16  // samples of a pixel per ray of the layout
 static_assert(FI_GROUP <= WF_SLOTS, "a sample group must fit the query slots of an entry");
 
 #ifndef FI_GROUPED_QUERIES
@@ -51,6 +52,7 @@ struct FiArgs {
   int *ent_cnt;
   int *ent_next;
   float2 *ent_u;
+  uint32_t *ent_mask;  // bit s - 16 grp: sample s of the entry's group collided
   float *qx, *qy, *qz, *wr, *wg, *wb;
   unsigned *count;
   int n_entries;     // compacted entries of the chunk (NEE kernel)
@@ -108,6 +110,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_sample_kernel(FiArgs a) {
   const uint32_t r = a.ray0 + (uint32_t)i;
   const MarchJob &job = a.job;
   int cnt = 0;
+  uint32_t hit_mask = 0u;
   bool pixel_ok = false;
   float u0 = 0.0f, u1 = 0.0f;
   if (active) {
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_sample_kernel(FiArgs a) {
             a.sr[q] = op.x;
             a.sg[q] = op.y;
             a.sb[q] = op.z;
+            hit_mask |= 1u << (smp - s0);
             ++cnt;
           }
         }
@@ -155,6 +159,7 @@ __global__ __launch_bounds__(WF_THREADS) void fi_sample_kernel(FiArgs a) {
       a.ent_cnt[t] = cnt;
       a.ent_next[t] = -1;
       a.ent_u[t] = make_float2(u0, u1);
+      a.ent_mask[t] = hit_mask;
       for (int k = 0; k < cnt; ++k) {
         const int64_t q = wf_slot(i, k), o = wf_slot(t, k);
         a.qx[o] = a.sx[q];
@@ -191,12 +196,15 @@ __global__ __launch_bounds__(WF_THREADS) void fi_nee_kernel(FiArgs a) {
   const float g = job.g;
   const float hg_c = (1.0f - g * g) * (0.25f / PFN_PI), hg_a = 1.0f + g * g, hg_b = 2.0f * g;
   f3 Sd = {0.f, 0.f, 0.f}, Si = {0.f, 0.f, 0.f};
+  uint32_t mask = a.ent_mask[t];
   for (int k = 0; k < cnt; ++k) {
     const int64_t q = wf_slot(t, k);
     const f3 x = {a.qx[q], a.qy[q], a.qz[q]};
     const f3 alb = {a.wr[q], a.wg[q], a.wb[q]};
+    const int smp = grp * FI_GROUP + __builtin_ctz(mask);  // the k-th set bit
+    mask &= mask - 1u;
     Philox rng;
-    rng.init(job.seed, pix * (uint64_t)a.spp + (uint64_t)(grp * FI_GROUP + k), STREAM_FI_NEE);
+    rng.init(job.seed, pix * (uint64_t)a.spp + (uint64_t)smp, STREAM_FI_NEE);
     f3 Ld = {0.f, 0.f, 0.f};
     for (int l = 0; l < a.m.n_lights; ++l) {
       if (!((job.light_mask >> l) & 1)) continue;
@@ -299,6 +307,7 @@ pfn_status run_first_interaction(pfn_context *ctx, const MarchArgs &m, MarchJob 
     a.ent_ray = b.ent_ray;
     a.ent_cnt = b.ent_cnt;
     a.ent_next = b.ent_next;
+    a.ent_mask = b.ent_mask;
     a.ent_u = b.ent_u;
     a.qx = b.slot[0];
     a.qy = b.slot[1];

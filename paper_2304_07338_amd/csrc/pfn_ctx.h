@@ -85,6 +85,7 @@ struct WfRound {
   int *ent_cnt = nullptr;
   int *ent_next = nullptr;
   float2 *ent_u = nullptr;
+  uint32_t *ent_mask = nullptr;  // first-interaction renderer: which samples of the entry collided
   float *slot[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // x y z, W rgb
   void *feat = nullptr;   // position features [level][slot]
   void *dfeat = nullptr;  // direction features [level][entry]

@@ -701,6 +701,7 @@ static void free_entries(WfState &w) {
     free_p(b.ent_cnt);
     free_p(b.ent_next);
     free_p(b.ent_u);
+    free_p(b.ent_mask);
     for (int k = 0; k < 6; ++k) free_p(b.slot[k]);
     free_p(b.feat);
     free_p(b.dfeat);
@@ -725,6 +726,7 @@ hipError_t wf_reserve(WfState &w, size_t entries, size_t rays, size_t feat_bytes
       if ((e = alloc_n(b.ent_cnt, entries))) return e;
       if ((e = alloc_n(b.ent_next, entries))) return e;
       if ((e = alloc_n(b.ent_u, entries))) return e;
+      if ((e = alloc_n(b.ent_mask, entries))) return e;
       for (int k = 0; k < 6; ++k)
         if ((e = alloc_n(b.slot[k], slots))) return e;
       unsigned char *fp = nullptr;
