@@ -5,10 +5,12 @@ the memory access pattern of a ray-marched frame does not depend on the paramete
 With --renderer first_interaction it renders the same view with the Algorithm 2 renderer at 1
 spp instead (at --width x --height).  With --train-steps N it then runs N training steps of the
 benchmark's recipe (batch 2^18, FP16 matrix cores) on the traced cache, for the training kernels'
-counters.
+counters.  With --paper-encoding the field is the paper's (16 levels x 8 features, growth 2, 5
+hidden layers) instead of the configuration's.
 
     python -m paper_2304_07338_amd.profile_run [--frames 3] [--strategy auto|fused|wavefront]
         [--renderer march|first_interaction] [--width 1920 --height 1080] [--train-steps 0]
+        [--paper-encoding]
 """
 import argparse
 import os
@@ -29,6 +31,8 @@ def main():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--train-steps", type=int, default=0)
+    ap.add_argument("--paper-encoding", action="store_true",
+                    help="the paper's field: 16 levels x 8 features, growth 2, 5 hidden layers")
     args = ap.parse_args()
     import torch
     from paper_2304_07338_amd import scenegen as sg
@@ -44,7 +48,9 @@ def main():
     ctx.set_lights(sg.lights_array(lights))
     ctx.build_light_volume(0.5)
     ctx.trace_photon_cache(1 << 22, wl.C1_G_BINS, cache_res=128, seed=6)
-    ctx.field_init(FieldConfig(), seed=1)
+    fc = FieldConfig(feats_per_level=8, growth=2.0, hidden_layers=5) if args.paper_encoding \
+        else FieldConfig()
+    ctx.field_init(fc, seed=1)
     cam0 = wl.camera(w, 0)
     cam = sg.Camera(cam0.eye, cam0.target, cam0.up, cam0.fov_y_deg, args.width, args.height)
     rc = RenderConfig(spp=1, step_voxels=0.5, max_steps=1024, t_min=1e-3, field_stride=4, g=0.4,
