@@ -966,7 +966,18 @@ pfn_status run_wavefront(pfn_context *ctx, const MarchArgs &m, std::vector<March
   PFN_HIP(ctx, hipStreamSynchronize(ctx->stream));
 
   std::vector<std::pair<int, int>> groups;
-  if (fd_host.levels >= 8 && fd_host.levels <= 16) {
+  if (fg > 1 && fd_host.levels >= 8) {
+    // 8 features per level: a hashed level's table is 4x the 2-feature one (8 MB at 2^19
+    // entries), two of them no longer share an XCD's L2 well; launches of up to 8 levels, one
+    // per XCD (measured on a 1080p frame, 16 levels at growth 2: 108 against 121 ms per frame
+    // with the levels paired).  Runs of 8, 4, 2, 1 levels, marked by the end -(level count).
+    for (int l = 0, left = fd_host.levels; left > 0;) {
+      const int take = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
+      groups.push_back({l, -take});
+      l += take;
+      left -= take;
+    }
+  } else if (fd_host.levels >= 8 && fd_host.levels <= 16) {
     // one launch, the levels paired over the XCDs; marked by a negative start
     groups.push_back({-1, fd_host.levels});
   } else {
