@@ -20,12 +20,12 @@ STEP_VOXELS = 0.5
 DENSE_EXT = 45.0  # extinction per cube length at opacity 1
 
 
-def _dense_ragged(seed=4):
+def _dense_ragged(seed=4, shape=(41, 30, 37)):
     """A 37 x 30 x 41 (nx, ny, nz) volume dense enough (with DENSE_EXT) that deep texels reach
     tau > 17.5."""
     import torch
     rng = np.random.default_rng(seed)
-    nz, ny, nx = 41, 30, 37
+    nz, ny, nx = shape
     z, y, x = np.meshgrid((np.arange(nz) + 0.5) / nz, (np.arange(ny) + 0.5) / ny,
                           (np.arange(nx) + 0.5) / nx, indexing="ij")
     d = 0.55 + 0.35 * np.sin(7 * x + 3 * y) * np.cos(5 * z) + 0.05 * rng.uniform(size=x.shape)
@@ -89,6 +89,17 @@ def test_light_grid_dense_ragged(orc, dtype):
     n_zero = _check_grid(orc, volume_as(vol, dtype), tf, lights, 250, 2, f"dense {dtype}",
                          ext=DENSE_EXT)
     assert n_zero > 20  # the early stop is exercised
+
+
+@pytest.mark.parametrize("dtype", ["f16"])
+def test_light_grid_long_volume(orc, dtype):
+    """A 900 x 12 x 14 volume: a side above 768 selects the binary16 march that keeps 16 steps'
+    loads in flight (smaller volumes take 8), with marches of up to about 1800 steps."""
+    vol, tf, lights = _dense_ragged(seed=5, shape=(14, 12, 900))
+    lights = np.array([[1.3, 0.5, 0.5, 1.0, 1.0, 1.0], [-0.2, 0.3, 0.6, 0.5, 0.6, 0.7],
+                       [0.5, 2.0, -1.0, 2.0, 2.0, 2.0]])
+    say(f"light grid, dense 900x12x14 {dtype} volume, 3 lights")
+    _check_grid(orc, volume_as(vol, dtype), tf, lights, 120, 3, f"long {dtype}", ext=8.0)
 
 
 def test_light_grid_not_built_is_an_error():
