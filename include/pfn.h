@@ -169,7 +169,8 @@ typedef struct {
   float growth;        /* per-level resolution factor in [1, 4]; N_l = floor(base_res * growth^l),
                           below 2^24 cells per axis (16 levels at growth 2 from 16 reach 2^19) */
   int log2_table;      /* hashed-level table size 2^log2_table (dense levels are exact) */
-  int hidden_layers;   /* ReLU hidden layers (1..7) of width 64, no biases, linear output */
+  int hidden_layers;   /* ReLU hidden layers (1..7) of width 64, no biases, linear output;
+                          the training calls take 1..5 (PFN_ERR_UNSUPPORTED above) */
   int width;           /* 64 */
   float psi;           /* log target encoding precision (Eq. 6/7) */
 } pfn_field_desc;
