@@ -54,9 +54,10 @@ def fctx():
 
 # (levels, hidden layers, log2 table size, features per level, growth): the configuration's
 # field, small ones, and the paper's encoding (8 features per level; 16 levels at growth 2 reach
-# 16 * 2^15 cells per axis)
+# 16 * 2^15 cells per axis), the last at its full size (T = 2^19, 101.8 M parameters)
 QUERY_CASES = [(16, 3, 19, 2, 1.5), (16, 1, 12, 2, 1.5), (7, 2, 10, 2, 1.5),
-               (16, 3, 19, 8, 1.5), (16, 5, 14, 8, 2.0), (6, 2, 10, 8, 1.5)]
+               (16, 3, 19, 8, 1.5), (16, 5, 14, 8, 2.0), (6, 2, 10, 8, 1.5),
+               (16, 5, 19, 8, 2.0)]
 
 
 @pytest.mark.parametrize("levels,hidden,log2_table,feats,growth", QUERY_CASES)

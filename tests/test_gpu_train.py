@@ -144,12 +144,14 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("levels,hidden,log2_table,feats,growth",
                          [(16, 3, 12, 2, 1.5), (8, 2, 12, 2, 1.5), (16, 1, 12, 2, 1.5),
-                          (16, 3, 19, 2, 1.5), (16, 3, 14, 8, 1.5), (16, 5, 16, 8, 2.0)])
+                          (16, 3, 19, 2, 1.5), (16, 3, 14, 8, 1.5), (16, 5, 16, 8, 2.0),
+                          (16, 5, 19, 8, 2.0)])
 def test_forward_backward_gradients(orc, tctx, levels, hidden, log2_table, feats, growth):
     """Loss and gradient of every grid level and weight matrix against the oracle.  With
     T = 2^19 (the benchmark's table) position levels 0-3 and direction levels 0-9 are dense, so
     both scatter branches are compared level by level; the paper's encoding (8 features per
-    level, 16 levels at growth 2) is compared the same way."""
+    level, 16 levels at growth 2) is compared the same way, also at its full size (T = 2^19,
+    position levels 0-2 dense)."""
     import torch
     from paper_2304_07338_amd.pfn import FieldConfig
     ctx, _ = tctx
@@ -175,8 +177,9 @@ def test_forward_backward_gradients(orc, tctx, levels, hidden, log2_table, feats
     dev = [torch.tensor(a, device="cuda:0") for a in (x, w, g, tgt)]
     segs = _segments(L, feats)
     if log2_table == 19 and levels == 16:
+        # dense position levels: 0-3 at growth 1.5 (N = 16 .. 54), 0-2 at growth 2 (16 .. 64)
         assert [k for k in segs if k.startswith("pos") and k.endswith("d")] == \
-            ["pos0d", "pos1d", "pos2d", "pos3d"]
+            ["pos0d", "pos1d", "pos2d", "pos3d"][:4 if growth == 1.5 else 3]
     for prec, rounding in (("f32", 0), ("f16", 1), ("bf16", 2)):
         loss, grad = ctx.field_forward_backward(*dev, precision=prec)
         grad = grad.cpu().numpy().astype(np.float64)
