@@ -503,16 +503,22 @@ void wf_field_kernel(WfFieldArgs a) {
 // The field kernel for 8 features per level (4 feature groups): the same tiles and sums as
 // wf_field_kernel; a lane loads 16 (FP32: 32) bytes per level and query, and word g of level
 // 4q+j goes to word j of feature group g's operand.  Its larger weight image sets its occupancy.
+// With 16-bit weights, workgroups of 8 waves share one copy of the weight image (about 70 KB
+// with 5 hidden layers), so two resident workgroups give 4 waves per SIMD; the FP32 image, twice
+// the size, keeps workgroups of 4 waves and the registers of one wave per SIMD.
 template <int P>
-__global__ __launch_bounds__(WF_THREADS) void wf_field8_kernel(WfFieldArgs a) {
+constexpr int wf8_threads() { return P == P_F32 ? 256 : 512; }
+template <int P>
+__global__ __launch_bounds__(wf8_threads<P>())
+__attribute__((amdgpu_waves_per_eu(P == P_F32 ? 1 : 4, 8))) void wf_field8_kernel(WfFieldArgs a) {
   extern __shared__ __align__(16) unsigned char lds_w[];
   stage_weights(lds_w, a.mlp, a.mlp_bytes);
   __syncthreads();
   constexpr int FG = 4;
   const FieldDev &F = *a.F;
   const int lane = lane_id(), q = lane >> 4, col = lane & 15;
-  const int waves = (int)gridDim.x * (WF_THREADS / 64);
-  const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (WF_THREADS / 64) +
+  const int waves = (int)gridDim.x * (wf8_threads<P>() / 64);
+  const int w0 = __builtin_amdgcn_readfirstlane((int)blockIdx.x * (wf8_threads<P>() / 64) +
                                                 (int)(threadIdx.x >> 6));
   const int n_tiles = (a.n_entries + 15) >> 4;
   for (int rt = w0; rt < n_tiles; rt += waves) {
@@ -611,13 +617,13 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field8_kernel(WfFieldArgs a) {
       const vec *w = reinterpret_cast<const vec *>(lds_w);
       f32x4 pre[4];
       mlp_input16_g<P, FG>(w, b1, M::pack(gz), pre);
-      for (int k = 0; k < kmax; ++k) {
-        const bool valid = k < cnt;
-        const int64_t sl = wf_slot(t, k);
-        u32x4 pwg[FG];
+      // the loads of query k+1 are issued before the network of query k runs
+      auto load_k = [&](int k, u32x4 (&pwg)[FG], f3 &W) {
 #pragma unroll
         for (int g = 0; g < FG; ++g) pwg[g] = u32x4{0u, 0u, 0u, 0u};
-        if (valid) {
+        W = {0.f, 0.f, 0.f};
+        if (k < cnt) {
+          const int64_t sl = wf_slot(t, k);
 #pragma unroll
           for (int j = 0; j < 4; ++j)
             if (4 * q + j < F.levels) {
@@ -627,17 +633,25 @@ __global__ __launch_bounds__(WF_THREADS) void wf_field8_kernel(WfFieldArgs a) {
               pwg[2][j] = w4.z;
               pwg[3][j] = w4.w;
             }
+          if (q == 0) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
         }
+      };
+      u32x4 pwg[FG];
+      f3 W;
+      load_k(0, pwg, W);
+      for (int k = 0; k < kmax; ++k) {
+        int wofs = 0;  // opaque offset: keeps the LDS weight reads inside the loop
+        asm volatile("" : "+s"(wofs));
         vec b0[FG];
 #pragma unroll
         for (int g = 0; g < FG; ++g) b0[g] = __builtin_bit_cast(vec, pwg[g]);
-        f3 W = {0.f, 0.f, 0.f};
-        if (q == 0 && valid) W = {a.wr[sl], a.wg[sl], a.wb[sl]};
-        const f32x4 out = mlp_rest16_g<P, FG>(w, F.hidden, b0, pre);
-        if (q == 0 && valid) {
-          S.x = fmaf(W.x, decode_lp(out[0], F.psi, F.kappa), S.x);
-          S.y = fmaf(W.y, decode_lp(out[1], F.psi, F.kappa), S.y);
-          S.z = fmaf(W.z, decode_lp(out[2], F.psi, F.kappa), S.z);
+        const f3 Wc = W;
+        if (k + 1 < kmax) load_k(k + 1, pwg, W);
+        const f32x4 out = mlp_rest16_g<P, FG>(w + wofs, F.hidden, b0, pre);
+        if (q == 0 && k < cnt) {
+          S.x = fmaf(Wc.x, decode_lp(out[0], F.psi, F.kappa), S.x);
+          S.y = fmaf(Wc.y, decode_lp(out[1], F.psi, F.kappa), S.y);
+          S.z = fmaf(Wc.z, decode_lp(out[2], F.psi, F.kappa), S.z);
         }
       }
     }
@@ -841,7 +855,7 @@ static hipError_t launch_k23(pfn_context *ctx, hipStream_t st, const WfEncArgs &
     hipLaunchKernelGGL((wf_field_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
                        (size_t)f.mlp_bytes, st, f);
   else
-    hipLaunchKernelGGL((wf_field8_kernel<P>), dim3(field_blocks), dim3(WF_THREADS),
+    hipLaunchKernelGGL((wf_field8_kernel<P>), dim3(field_blocks), dim3(wf8_threads<P>()),
                        (size_t)f.mlp_bytes, st, f);
   timing_end_on(ctx, ts, TK_WF_FIELD, st);
   return hipSuccess;
@@ -878,7 +892,7 @@ static int field_blocks_resident(int mlp_bytes, int fg) {
       fg == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field_kernel<P>,
                                                              WF_THREADS, (size_t)mlp_bytes)
               : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, wf_field8_kernel<P>,
-                                                             WF_THREADS, (size_t)mlp_bytes);
+                                                             wf8_threads<P>(), (size_t)mlp_bytes);
   if (e != hipSuccess || per_cu < 1) per_cu = 1;
   int cus = 256;
   int dev = 0;
