@@ -337,8 +337,9 @@ pfn_status pfn_image_error(pfn_context *ctx, const float *dev_img, const float *
 pfn_status pfn_image_error_noalloc(pfn_context *ctx, const float *dev_img, const float *dev_ref,
                                    int64_t n, double *dev_result);
 
-/* Tile shape of the ray-march launch: each wave covers tile_w x (64 / tile_w) pixels and a
- * workgroup block_w x block_h waves (block_w * block_h = 4).  Chosen by the autotuner. */
+/* Tile shape of the ray-march launch: each wave covers tile_w x (64 / tile_w) pixels (tile_w a
+ * power of two, 1..64) and a workgroup block_w x block_h waves (block_w * block_h = 4).  Chosen
+ * by the autotuner among tile_w 4, 8, 16 and 32. */
 pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int block_h);
 /* Launch mode of the ray march: persistent_per_cu = 0 launches one workgroup per pixel block;
  * k > 0 launches k workgroups per compute unit that pull blocks from per-XCD queues until all

@@ -1008,8 +1008,8 @@ extern "C" pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy) {
 
 extern "C" pfn_status pfn_set_tile_config(pfn_context *ctx, int tile_w, int block_w, int block_h) {
   CHECK_CTX(ctx);
-  ARG(tile_w == 8 || tile_w == 16 || tile_w == 32 || tile_w == 64 || tile_w == 4,
-      "tile_w in {4, 8, 16, 32, 64}");
+  ARG(tile_w >= 1 && tile_w <= 64 && (tile_w & (tile_w - 1)) == 0,
+      "tile_w in {1, 2, 4, 8, 16, 32, 64}");
   ARG(block_w >= 1 && block_h >= 1 && block_w * block_h == 4, "block_w * block_h must be 4");
   ctx->tile.tile_w = tile_w;
   ctx->tile.tile_h = 64 / tile_w;
@@ -1116,7 +1116,7 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
       }
       // candidates: the fused kernel in every tile shape, block arrangement and launch mode;
       // the wavefront rounds in every tile shape (the march kernel's ray tiles)
-      const int tws[3] = {8, 16, 32};
+      const int tws[4] = {4, 8, 16, 32};
       const int arr[3][2] = {{2, 2}, {4, 1}, {1, 4}};
       const int pers[3] = {0, 2, 4};
       std::vector<TileConfig> cands;
