@@ -175,7 +175,7 @@ def test_render_with_field_parity(orc, strategy):
 
 def test_render_with_wide_field(orc):
     """A field of 8 features per level (the paper's encoding) lights the wavefront form of the
-    ray marcher (FP32 and FP16 against the oracle); the fused kernel refuses it."""
+    ray marcher (FP32, BF16 and FP16 against the oracle); the fused kernel refuses it."""
     import torch
     from paper_2304_07338_amd import scenegen as sg
     from paper_2304_07338_amd.pfn import FieldConfig, PfnError, RenderConfig, INDIRECT_FIELD
@@ -192,7 +192,8 @@ def test_render_with_wide_field(orc):
     ctx.field_set_kappa(5e-3)
     cam = sg.make_camera(w.seed, 4, 24, 20)
     os_ = oracle_scene(orc, vol, tf, lights)
-    for prec, rounding, tol, tol_max in (("f32", 0, 1e-4, 5e-5), ("f16", 1, 3e-4, 2e-4)):
+    for prec, rounding, tol, tol_max in (("f32", 0, 1e-4, 5e-5), ("bf16", 2, 8e-4, 5e-4),
+                                         ("f16", 1, 3e-4, 2e-4)):
         img = ctx.render_frame(cam, RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3,
                                                  field_precision=prec))
         ctx.sync()
