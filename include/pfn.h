@@ -134,7 +134,9 @@ pfn_status pfn_cache_info(pfn_context *ctx, int *host_n_bins, int *host_res, dou
  * takes n records from device arrays (positions in [0,1]^3, unit incident directions and
  * incident powers [n][3], bins in [0, n_bins); records with a bin outside that range are
  * skipped).  Both need the volume and transfer function (for sigma_t) and synchronise.
- * grid_res in [1, 128]; device memory: 36 B per record plus 4 B x (n_bins grid_res^3 + 1). */
+ * grid_res in [1, 128]; device memory: 36 B per record plus 4 B x (n_bins grid_res^3 + 1) plus
+ * 4 B per source record while building.  The map holds fewer than 2^32 records: n < 2^32, and
+ * pfn_photon_map_build refuses (PFN_ERR_INVALID_ARG) a trace that kept 2^32 or more. */
 pfn_status pfn_photon_map_build(pfn_context *ctx, int grid_res);
 pfn_status pfn_photon_map_set(pfn_context *ctx, const float *dev_x, const float *dev_w,
                               const float *dev_power, const int32_t *dev_bin, uint64_t n,
@@ -154,7 +156,8 @@ pfn_status pfn_photon_map_get(pfn_context *ctx, uint32_t *dev_cell_start, size_t
  *          distance to the farthest of them (all records within `radius` if there are at most
  *          k; none gives 0).
  * Writes rgb [n][3] and, if not NULL, r [n] and the record count [n].  More than 256 records at
- * one distance (to 2^-40 of the radius) at the K-th place are cut to 256.  radius in (0, 2]. */
+ * one distance (to 2^-40 of the radius) at the K-th place are cut to 256.  radius in (0, 2];
+ * n < 2^31 (one wavefront per query; more than 2^24 queries run as several launches). */
 pfn_status pfn_photon_map_estimate(pfn_context *ctx, const float *dev_xyz, const float *dev_dir,
                                    const int32_t *dev_bin, int64_t n, float radius, int k,
                                    float *dev_rgb, float *dev_r, int32_t *dev_count);
@@ -189,7 +192,8 @@ pfn_status pfn_field_set_kappa(pfn_context *ctx, double kappa);
 /* Field inference (Eq. 2) at n points: xyz in [0,1]^3, unit directions (the view direction
  * pointing back along the ray), g.  Writes the raw network output L' (n x 3) and, if dev_rgb is
  * not NULL, the decoded radiance kappa * 10^(-psi L') (Eq. 7).  precision: arithmetic of the
- * grid features and MLP (F32, F16 or BF16 matrix cores, FP32 accumulation). */
+ * grid features and MLP (F32, F16 or BF16 matrix cores, FP32 accumulation).  n < 2^38; more
+ * than 2^30 queries run as several launches. */
 pfn_status pfn_field_query(pfn_context *ctx, pfn_dtype precision, const float *dev_xyz,
                            const float *dev_dir, const float *dev_g, int64_t n,
                            float *dev_lprime, float *dev_rgb);
@@ -247,7 +251,9 @@ pfn_status pfn_train_step_radius(const pfn_train_params *params, int step, float
 pfn_status pfn_train_lr_at(const pfn_train_params *params, int step, float *host_lr);
 /* The training-batch generator alone (for checking): step `step`'s n samples, g_sampling as in
  * pfn_train_params (with one bin, 1 acts as 0).  dev_bin receives the sample's bin (uniform g:
- * the lower of the two neighbouring bins).  PFN_ERR_NOT_READY without a cache. */
+ * the lower of the two neighbouring bins).  Any output may be NULL.  n in [0, 2^32] (sample i
+ * draws from counter (step, i), so 2^32 samples are all distinct).  PFN_ERR_NOT_READY without a
+ * cache. */
 pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t step, int64_t n,
                            int g_sampling, float *dev_xyz, float *dev_dir, float *dev_g,
                            int32_t *dev_bin, float *dev_target);

@@ -121,6 +121,10 @@ void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *ca
 void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache,
                           double kappa, double psi, int g_mode, double *xyz, double *dir,
                           double *g, int *bin, double *target);
+/* Samples first .. first + n - 1 of the same batch, written to rows 0 .. n - 1. */
+void orc_train_batch_range(uint64_t seed, int64_t step, int64_t first, int64_t n,
+                           const orc_cache *cache, double kappa, double psi, int g_mode,
+                           double *xyz, double *dir, double *g, int *bin, double *target);
 
 /* ---------------- Photon tracing (Algorithm 1) ---------------- */
 typedef struct {

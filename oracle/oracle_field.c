@@ -369,14 +369,16 @@ double orc_lr_at(int64_t step, double lr0, double decay, int64_t start_step, int
  * (a uniformly drawn bin, the target that bin's gather); g_mode 1 turns the same uniform draw
  * into g uniform over [g_0, g_last] and takes as target the gather interpolated linearly in g
  * between the two neighbouring bins (the same interpolation as the renderer's cache gather),
- * reporting the lower bin. */
-void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache,
-                          double kappa, double psi, int g_mode, double *xyz, double *dir,
-                          double *g, int *bin, double *target) {
+ * reporting the lower bin.  Samples first .. first + n - 1 of the batch go to rows 0 .. n - 1
+ * (sample i draws from counter (step, i)). */
+void orc_train_batch_range(uint64_t seed, int64_t step, int64_t first, int64_t n,
+                           const orc_cache *cache, double kappa, double psi, int g_mode,
+                           double *xyz, double *dir, double *g, int *bin, double *target) {
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
     orc_rng r;
-    orc_rng_init(&r, seed, ((uint64_t)step << 32) | (uint64_t)(uint32_t)i, ORC_STREAM_TRAIN);
+    orc_rng_init(&r, seed, ((uint64_t)step << 32) | (uint64_t)(uint32_t)(first + i),
+                 ORC_STREAM_TRAIN);
     double x[3];
     for (int a = 0; a < 3; ++a) x[a] = orc_rng_next(&r);
     const double u = orc_rng_next(&r);
@@ -405,6 +407,12 @@ void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cach
     if (bin) bin[i] = b;
     for (int c = 0; c < 3; ++c) target[3 * i + c] = orc_log_encode(v[c] / kappa, psi);
   }
+}
+
+void orc_train_batch_mode(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache,
+                          double kappa, double psi, int g_mode, double *xyz, double *dir,
+                          double *g, int *bin, double *target) {
+  orc_train_batch_range(seed, step, 0, n, cache, kappa, psi, g_mode, xyz, dir, g, bin, target);
 }
 
 void orc_train_batch(uint64_t seed, int64_t step, int64_t n, const orc_cache *cache, double kappa,

@@ -148,6 +148,9 @@ def lib():
                                       C.c_double, C.c_double, dp, dp, dp, ip, dp]
         L.orc_train_batch_mode.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.POINTER(Cache),
                                            C.c_double, C.c_double, C.c_int, dp, dp, dp, ip, dp]
+        L.orc_train_batch_range.argtypes = [C.c_uint64, C.c_int64, C.c_int64, C.c_int64,
+                                            C.POINTER(Cache), C.c_double, C.c_double, C.c_int,
+                                            dp, dp, dp, ip, dp]
         L.orc_trace.argtypes = [C.POINTER(Scene), C.POINTER(TraceParams), C.c_uint64, C.c_uint64,
                                 C.POINTER(TraceStats), C.c_uint64, dp, dp, dp, ip, u64p, u64p]
         L.orc_splat_cache.restype = C.c_double
@@ -359,17 +362,18 @@ def lr_at(step, lr0=9e-4, decay=0.92, start_step=1400, interval=25) -> float:
     return lib().orc_lr_at(step, lr0, decay, start_step, interval)
 
 
-def train_batch(seed, step, n, cache: OracleCache, kappa, psi=5.0, g_sampling="pool"):
+def train_batch(seed, step, n, cache: OracleCache, kappa, psi=5.0, g_sampling="pool", first=0):
     """g_sampling "pool": g from the cache's bins; "uniform": g uniform over [g_0, g_last] with
-    targets interpolated linearly in g between the neighbouring bins."""
+    targets interpolated linearly in g between the neighbouring bins.  Returns samples
+    first .. first + n - 1 of the batch."""
     xyz = np.zeros((n, 3))
     dirs = np.zeros((n, 3))
     g = np.zeros(n)
     b = np.zeros(n, dtype=np.int32)
     tgt = np.zeros((n, 3))
     mode = {"pool": 0, "uniform": 1}[g_sampling]
-    lib().orc_train_batch_mode(seed, step, n, cache.ref, kappa, psi, mode, _ptr(xyz), _ptr(dirs),
-                               _ptr(g), _ptr(b, ip), _ptr(tgt))
+    lib().orc_train_batch_range(seed, step, first, n, cache.ref, kappa, psi, mode, _ptr(xyz),
+                                _ptr(dirs), _ptr(g), _ptr(b, ip), _ptr(tgt))
     return xyz, dirs, g, b, tgt
 
 

@@ -911,6 +911,8 @@ extern "C" pfn_status pfn_photon_map_build(pfn_context *ctx, int grid_res) {
   pfn_status st = need_scene(ctx);
   if (st) return st;
   if (ctx->rec_photons == 0) return pfn_fail(ctx, PFN_ERR_NOT_READY, "no trace yet");
+  // the sorted map's offsets are 32-bit
+  ARG(ctx->rec_count < ((uint64_t)1 << 32), "the photon map takes fewer than 2^32 records");
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   PmSrcHost src{ctx->rec_x, ctx->rec_w, ctx->rec_p, ctx->rec_bin, ctx->rec_cnt, ctx->rec_maxrec,
                 ctx->rec_photons * (uint64_t)ctx->rec_maxrec};

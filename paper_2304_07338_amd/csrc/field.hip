@@ -279,29 +279,23 @@ hipError_t launch_field_query(pfn_context *ctx, const FieldSlot &f, int prec, co
   FieldDev F = make_field_dev(f, prec);
   const int fg = f.desc.feats_per_level / 2;
   int bytes = mlp_packed_elems(prec, f.desc.hidden_layers, fg) * (prec == P_F32 ? 4 : 2);
-  int64_t blocks = (n + QUERY_THREADS - 1) / QUERY_THREADS;
-  if (blocks < 1) blocks = 1;
-  const dim3 gr((unsigned)blocks), bl(QUERY_THREADS);
-  if (fg == 1) {
-    if (prec == P_F32)
-      hipLaunchKernelGGL((field_query_kernel<P_F32, 1>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-    else if (prec == P_BF16)
-      hipLaunchKernelGGL((field_query_kernel<P_BF16, 1>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-    else
-      hipLaunchKernelGGL((field_query_kernel<P_F16, 1>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-  } else {
-    if (prec == P_F32)
-      hipLaunchKernelGGL((field_query_kernel<P_F32, 4>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-    else if (prec == P_BF16)
-      hipLaunchKernelGGL((field_query_kernel<P_BF16, 4>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
-    else
-      hipLaunchKernelGGL((field_query_kernel<P_F16, 4>), gr, bl, bytes, ctx->stream, F,
-                         f.mlp_packed[prec], bytes, xyz, dir, g, n, lp, rgb);
+  auto kernel = [&]() {
+    if (fg == 1)
+      return prec == P_F32    ? field_query_kernel<P_F32, 1>
+             : prec == P_BF16 ? field_query_kernel<P_BF16, 1>
+                              : field_query_kernel<P_F16, 1>;
+    return prec == P_F32    ? field_query_kernel<P_F32, 4>
+           : prec == P_BF16 ? field_query_kernel<P_BF16, 4>
+                            : field_query_kernel<P_F16, 4>;
+  }();
+  // one work-item per query; batches beyond one dispatch's reach go in pieces
+  for (int64_t o = 0; o < n; o += PFN_DISPATCH_ITEMS) {
+    const int64_t m = std::min<int64_t>(n - o, PFN_DISPATCH_ITEMS);
+    const dim3 gr((unsigned)((m + QUERY_THREADS - 1) / QUERY_THREADS)), bl(QUERY_THREADS);
+    hipLaunchKernelGGL(kernel, gr, bl, bytes, ctx->stream, F, f.mlp_packed[prec], bytes,
+                       xyz + 3 * o, dir + 3 * o, g + o, m, lp + 3 * o, rgb ? rgb + 3 * o : nullptr);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }

@@ -14,6 +14,10 @@
 #include "pfn_field_dev.h"
 
 #define PFN_MAX_FIELDS 8
+// A dispatch's grid holds fewer than 2^32 work-items per dimension (the dispatch packet's grid
+// size is a 32-bit count), so launches over batches that may be larger are split into pieces of
+// at most this many work-items.
+#define PFN_DISPATCH_ITEMS ((int64_t)1 << 30)
 
 struct FieldSlot {
   bool init = false;

@@ -30,6 +30,8 @@ struct PmSrc {
   const uint8_t *cnt;  // records per photon (slotted trace records), or NULL: every slot valid
   int maxrec;
   uint64_t n_slots;
+  uint64_t i0;         // first slot of this launch (a build over more slots than one dispatch
+                       // holds runs in pieces)
 };
 
 __device__ __forceinline__ bool pm_valid(const PmSrc &s, uint64_t i) {
@@ -45,7 +47,7 @@ __device__ __forceinline__ int pm_cell(float v, int G) {
 
 __global__ void pm_count_kernel(PmSrc s, int G, int n_bins, uint32_t *__restrict__ counts,
                                 uint32_t *__restrict__ keys) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = s.i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= s.n_slots) return;
   uint32_t key = 0xFFFFFFFFu;
   if (pm_valid(s, i)) {
@@ -112,7 +114,7 @@ struct PmScatterArgs {
 
 template <typename VT>
 __global__ void pm_scatter_kernel(PmScatterArgs a) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = a.s.i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.s.n_slots) return;
   const uint32_t key = a.keys[i];
   if (key == 0xFFFFFFFFu) return;
@@ -135,7 +137,7 @@ struct PmEstArgs {
   float g_bins[8];
   const float *qx, *qw;
   const int32_t *qbin;
-  int64_t n;
+  int64_t q0, n;        // queries q0 .. n-1 (one wave each; larger batches run in pieces)
   float radius;
   int k;
   float *out, *r_out;
@@ -253,7 +255,7 @@ __device__ __forceinline__ int pm_crossing(const PmWaveLds &L, uint32_t need, ui
 template <bool KNN>
 __global__ __launch_bounds__(64) void pm_estimate_kernel(PmEstArgs a) {
   __shared__ PmWaveLds L;
-  const int64_t q = blockIdx.x;
+  const int64_t q = a.q0 + blockIdx.x;
   if (q >= a.n) return;
   const int lane = lane_id();
   const f3 x = {a.qx[3 * q], a.qx[3 * q + 1], a.qx[3 * q + 2]};
@@ -472,13 +474,18 @@ pfn_status pm_build(pfn_context *ctx, const PmSrcHost &src, int n_bins, const fl
     m.slot_cap = src.n_slots;
   }
   hipStream_t st = ctx->stream;
-  PmSrc s{src.x, src.w, src.p, src.bin, src.cnt, src.maxrec, src.n_slots};
+  PmSrc s{src.x, src.w, src.p, src.bin, src.cnt, src.maxrec, src.n_slots, 0};
   PFN_HIP(ctx, hipMemsetAsync(m.counts, 0, sizeof(uint32_t) * (n_keys + 1), st));
-  const unsigned blocks = (unsigned)((src.n_slots + 255) / 256);
-  if (src.n_slots > 0)
-    hipLaunchKernelGGL(pm_count_kernel, dim3(blocks), dim3(256), 0, st, s, G, n_bins, m.counts,
-                       m.keys);
-  PFN_HIP(ctx, hipGetLastError());
+  // one work-item per slot, in pieces of at most PFN_DISPATCH_ITEMS slots
+  const uint64_t piece = (uint64_t)PFN_DISPATCH_ITEMS;
+  auto piece_blocks = [&](uint64_t i0) {
+    return dim3((unsigned)((std::min(src.n_slots - i0, piece) + 255) / 256));
+  };
+  for (s.i0 = 0; s.i0 < src.n_slots; s.i0 += piece) {
+    hipLaunchKernelGGL(pm_count_kernel, piece_blocks(s.i0), dim3(256), 0, st, s, G, n_bins,
+                       m.counts, m.keys);
+    PFN_HIP(ctx, hipGetLastError());
+  }
   PFN_HIP(ctx, pm_scan(m, m.counts, m.start, n_keys + 1, 0, st));
   uint32_t total = 0;
   PFN_HIP(ctx, hipMemcpyAsync(&total, m.start + n_keys, 4, hipMemcpyDeviceToHost, st));
@@ -511,13 +518,13 @@ pfn_status pm_build(pfn_context *ctx, const PmSrcHost &src, int n_bins, const fl
   a.ra = m.ra;
   a.rb = m.rb;
   a.rc = m.rc;
-  if (src.n_slots > 0) {
+  for (a.s.i0 = 0; a.s.i0 < src.n_slots; a.s.i0 += piece) {
     if (ctx->vol_dtype == PFN_F16)
-      hipLaunchKernelGGL(pm_scatter_kernel<__half>, dim3(blocks), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(pm_scatter_kernel<__half>, piece_blocks(a.s.i0), dim3(256), 0, st, a);
     else
-      hipLaunchKernelGGL(pm_scatter_kernel<float>, dim3(blocks), dim3(256), 0, st, a);
+      hipLaunchKernelGGL(pm_scatter_kernel<float>, piece_blocks(a.s.i0), dim3(256), 0, st, a);
+    PFN_HIP(ctx, hipGetLastError());
   }
-  PFN_HIP(ctx, hipGetLastError());
   PFN_HIP(ctx, hipStreamSynchronize(st));
   m.n = total;
   m.grid = G;
@@ -548,18 +555,24 @@ hipError_t pm_launch_estimate(pfn_context *ctx, const float *xyz, const float *d
   a.out = out;
   a.r_out = r_out;
   a.n_out = n_out;
-  if (n <= 0) return hipSuccess;
-  if (k > 0)
-    hipLaunchKernelGGL(pm_estimate_kernel<true>, dim3((unsigned)n), dim3(64), 0, st, a);
-  else
-    hipLaunchKernelGGL(pm_estimate_kernel<false>, dim3((unsigned)n), dim3(64), 0, st, a);
-  return hipGetLastError();
+  // 64 work-items per query: at most PFN_DISPATCH_ITEMS / 64 queries per launch
+  const int64_t piece = PFN_DISPATCH_ITEMS / 64;
+  for (a.q0 = 0; a.q0 < n; a.q0 += piece) {
+    const dim3 gr((unsigned)std::min<int64_t>(n - a.q0, piece));
+    if (k > 0)
+      hipLaunchKernelGGL(pm_estimate_kernel<true>, gr, dim3(64), 0, st, a);
+    else
+      hipLaunchKernelGGL(pm_estimate_kernel<false>, gr, dim3(64), 0, st, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 __global__ void pm_unpack_kernel(const float4 *__restrict__ ra, const float4 *__restrict__ rb,
-                                 const float *__restrict__ rc, uint64_t n, float *pos, float *dir,
-                                 float *score) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                 const float *__restrict__ rc, uint64_t i0, uint64_t n, float *pos,
+                                 float *dir, float *score) {
+  const uint64_t i = i0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float4 a = ra[i], b = rb[i];
   if (pos) {
@@ -580,9 +593,14 @@ __global__ void pm_unpack_kernel(const float4 *__restrict__ ra, const float4 *__
 }
 
 hipError_t pm_launch_unpack(pfn_context *ctx, float *pos, float *dir, float *score, uint64_t n) {
-  if (n == 0) return hipSuccess;
   const PhotonMapState &m = ctx->pmap;
-  hipLaunchKernelGGL(pm_unpack_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     ctx->stream, m.ra, m.rb, m.rc, n, pos, dir, score);
-  return hipGetLastError();
+  const uint64_t piece = (uint64_t)PFN_DISPATCH_ITEMS;
+  for (uint64_t i0 = 0; i0 < n; i0 += piece) {
+    const uint64_t c = std::min(n - i0, piece);
+    hipLaunchKernelGGL(pm_unpack_kernel, dim3((unsigned)((c + 255) / 256)), dim3(256), 0,
+                       ctx->stream, m.ra, m.rb, m.rc, i0, n, pos, dir, score);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }

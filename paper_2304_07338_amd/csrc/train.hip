@@ -88,9 +88,10 @@ __device__ __forceinline__ void gen_sample(const SampleSrc &s, int64_t i, f3 &x,
   tgt[2] = log_target(v2 * s.inv_kappa, s.psi);
 }
 
-__global__ void train_batch_kernel(SampleSrc s, int64_t n, float *xyz, float *dir, float *g,
-                                   int32_t *bin, float *tgt) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Samples i0 .. n-1 (a piece of a batch that one dispatch cannot hold starts at i0 > 0).
+__global__ void train_batch_kernel(SampleSrc s, int64_t i0, int64_t n, float *xyz, float *dir,
+                                   float *g, int32_t *bin, float *tgt) {
+  int64_t i = i0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   f3 x, w;
   float gg, t[3];
@@ -1021,9 +1022,12 @@ extern "C" pfn_status pfn_train_batch(pfn_context *ctx, uint64_t seed, int64_t s
   PFN_HIP(ctx, hipSetDevice(ctx->device));
   float psi = ctx->fields[ctx->cur_field].init ? ctx->fields[ctx->cur_field].desc.psi : 5.0f;
   SampleSrc s = make_src(ctx, seed, step, psi, g_sampling);
-  hipLaunchKernelGGL(train_batch_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     ctx->stream, s, n, xyz, dir, g, bin, tgt);
-  PFN_HIP(ctx, hipGetLastError());
+  for (int64_t o = 0; o < n; o += PFN_DISPATCH_ITEMS) {
+    const int64_t m = std::min<int64_t>(n - o, PFN_DISPATCH_ITEMS);
+    hipLaunchKernelGGL(train_batch_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0,
+                       ctx->stream, s, o, o + m, xyz, dir, g, bin, tgt);
+    PFN_HIP(ctx, hipGetLastError());
+  }
   return PFN_OK;
 }
 
@@ -1195,7 +1199,7 @@ extern "C" pfn_status pfn_train_field(pfn_context *ctx, const pfn_train_params *
       // the step's batch (the same samples as the cache targets would use), its Eq. (5)
       // estimates and their Eq. (6) encoding
       const unsigned nb = (unsigned)((n + 255) / 256);
-      hipLaunchKernelGGL(train_batch_kernel, dim3(nb), dim3(256), 0, ctx->stream, src, n, b_xyz,
+      hipLaunchKernelGGL(train_batch_kernel, dim3(nb), dim3(256), 0, ctx->stream, src, 0, n, b_xyz,
                          b_dir, b_g, b_bin, nullptr);
       PFN_HIP(ctx, hipGetLastError());
       const int ts = timing_begin(ctx);

@@ -298,6 +298,10 @@ def test_training_batch_distribution_and_targets(orc):
     xyz3 = orc.train_batch(123, 7, 10, cache, kappa)[0]
     assert not np.allclose(xyz2, xyz[:10])
     np.testing.assert_array_equal(xyz3, xyz[:10])
+    # a range of the batch: the same samples as rows first .. first + n - 1 of the whole batch
+    part = orc.train_batch(123, 7, 40, cache, kappa, first=9000)
+    for a, whole in zip(part, (xyz, dirs, g, b, tgt)):
+        np.testing.assert_array_equal(a, whole[9000:9040])
 
 
 def test_uniform_g_batch_pins(orc):
