@@ -380,13 +380,15 @@ typedef enum {
 } pfn_strategy;
 pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy);
 /* Autotuner: time on this batch (iters launches each, after one warm-up launch) the render
- * forms the strategy allows (PFN_STRATEGY_AUTO: the fused kernel and, for field-lit batches, the
- * overlapped wavefront rounds; any other strategy: that form alone):
+ * forms that the strategy last set by pfn_set_render_strategy allows (PFN_STRATEGY_AUTO, the
+ * default: the fused kernel and, for field-lit batches, the overlapped wavefront rounds; any
+ * other strategy: that form alone):
  *   - the fused kernel in every tile shape / block arrangement / launch mode, replayed from
  *     captured graphs if pfn_set_launch_mode asked for graphs;
  *   - the wavefront rounds in every tile shape.
  * It keeps the fastest for the context (tile shape, launch mode, and the render strategy, which
- * becomes that form) and returns it.  Results are cached per batch shape and form (for the fused
+ * becomes that form until the next autotune or pfn_set_render_strategy; a later autotune again
+ * tries every form the caller's strategy allows) and returns it.  Results are cached per batch shape and form (for the fused
  * kernel, also per graph setting).  host_strategy receives the chosen pfn_strategy; host_ms the
  * time of one launch of the batch in it; any output pointer may be NULL. */
 pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job *host_jobs, int n_jobs,

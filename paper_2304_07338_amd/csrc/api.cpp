@@ -1004,7 +1004,7 @@ extern "C" pfn_status pfn_set_render_strategy(pfn_context *ctx, int strategy) {
   ARG(strategy == PFN_STRATEGY_AUTO || strategy == PFN_STRATEGY_FUSED ||
           strategy == PFN_STRATEGY_WAVEFRONT || strategy == PFN_STRATEGY_WAVEFRONT_SERIAL,
       "strategy is PFN_STRATEGY_AUTO, _FUSED, _WAVEFRONT or _WAVEFRONT_SERIAL");
-  ctx->strategy = strategy;
+  ctx->strategy = ctx->user_strategy = strategy;
   return PFN_OK;
 }
 
@@ -1071,10 +1071,11 @@ extern "C" pfn_status pfn_autotune_batch(pfn_context *ctx, const pfn_render_job 
   const int feats = field_lit ? ctx->fields[jobs[0].params.field_slot].desc.feats_per_level : 0;
   put(&feats, sizeof(int));
   // forms to time: the one the caller fixed, else the fused kernel (fields of 2 features per
-  // level) and (field-lit batches) the overlapped wavefront rounds
+  // level) and (field-lit batches) the overlapped wavefront rounds.  A form an earlier autotune
+  // chose does not narrow them: the caller's setting decides.
   const int saved_strategy = ctx->strategy;
   std::vector<int> forms;
-  if (saved_strategy != PFN_STRATEGY_AUTO) forms.push_back(saved_strategy);
+  if (ctx->user_strategy != PFN_STRATEGY_AUTO) forms.push_back(ctx->user_strategy);
   else {
     if (feats != 8) forms.push_back(PFN_STRATEGY_FUSED);
     if (field_lit) forms.push_back(PFN_STRATEGY_WAVEFRONT);

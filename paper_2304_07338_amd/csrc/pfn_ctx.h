@@ -178,6 +178,7 @@ struct pfn_context {
   std::vector<MarchGraph> graphs;
   std::vector<TunedEntry> tuned;  // autotuner cache, one entry per batch shape and render form
   int strategy = PFN_STRATEGY_AUTO;  // field renders: fused kernel or wavefront rounds
+  int user_strategy = PFN_STRATEGY_AUTO;  // the caller's setting: the forms the autotuner tries
   WfState wf;
   PhotonMapState pmap;
   float *pm_batch = nullptr;  // training batch with photon-map targets

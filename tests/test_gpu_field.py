@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from gpu_common import (check_err, coord_sensitivity, gpu_context, oracle_scene, rel_rmse, say,
-                        scene_arrays)
+                        scene_arrays, smooth_cache)
 
 pytestmark = pytest.mark.gpu
 
@@ -178,7 +178,8 @@ def test_render_with_wide_field(orc):
     ray marcher (FP32, BF16 and FP16 against the oracle); the fused kernel refuses it."""
     import torch
     from paper_2304_07338_amd import scenegen as sg
-    from paper_2304_07338_amd.pfn import FieldConfig, PfnError, RenderConfig, INDIRECT_FIELD
+    from paper_2304_07338_amd.pfn import (FieldConfig, PfnError, RenderConfig, INDIRECT_CACHE,
+                                          INDIRECT_FIELD)
     say("render with an 8-feature field, stride 4, 24x20 (wavefront)")
     w, vol, tf, lights = scene_arrays("c0")
     ctx = gpu_context(vol, tf, lights)
@@ -206,8 +207,14 @@ def test_render_with_wide_field(orc):
     with pytest.raises(PfnError) as e:
         ctx.render_frame(cam, RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3))
     assert e.value.status == -5
-    # the autotuner times the wavefront form only, and graph replay leaves it in place
+    # the autotuner times the wavefront form only, and graph replay leaves it in place; an
+    # earlier autotune of a cache-lit frame (which chooses the fused kernel) does not narrow it
     ctx.set_render_strategy("auto")
+    cache = smooth_cache(16, 2, seed=3)
+    ctx.set_cache(torch.tensor(cache, dtype=torch.float32, device="cuda:0"), [-0.5, 0.5],
+                  float(cache.max()))
+    rc_cache = RenderConfig(indirect=INDIRECT_CACHE, field_stride=4, g=0.3)
+    assert ctx.autotune_batch([cam], [rc_cache], iters=1)["strategy"] == "fused"
     ctx.set_launch_mode(0, use_graph=True)
     rc = RenderConfig(indirect=INDIRECT_FIELD, field_stride=4, g=0.3, field_precision="f16")
     best = ctx.autotune_batch([cam], [rc], iters=1)
