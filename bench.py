@@ -254,7 +254,8 @@ def main():
 
     fi_info = None if args.no_first_interaction else first_interaction_bench(ctx, cam, rc, args)
     variants = None if args.no_variants else frame_variants(ctx, cam, rc, out, args)
-    matched = None if args.no_matched else matched_rmse_frame(ctx, cam, rc, out, ms_per_step, args)
+    matched = None if args.no_matched else matched_rmse_frame(ctx, cam, rc, out, ms_per_step,
+                                                              cache_ms, args)
 
     result = {
         "metric": "1080p fps + field queries/s: photon field vs path tracer at matched RMSE",
@@ -444,13 +445,14 @@ def paper_encoding_costs(ctx, cam, rc, out, reps):
     return res
 
 
-def matched_rmse_frame(ctx, cam, rc, out, field_ms, args):
+def matched_rmse_frame(ctx, cam, rc, out, field_ms, cache_ms, args):
     """The benchmark frame against the Monte Carlo path tracer at equal error (the comparison
     of Section 4.3.1, on this GPU): a path-traced reference of --mr2-ref-spp samples (8 bounces,
     HG sampling, Russian roulette from bounce 3), the field frame as timed (1 spp), the plain
     cache gather, and the path tracer at 16..256 spp.  The path tracer's squared error is fitted
     as c^2 (1/spp + 1/ref_spp), solved for the spp at which it equals the field's, and its time
-    interpolated there; the speedup is that time over the field frame's."""
+    interpolated there; the speedup is that time over the field frame's.  Both frames' times
+    are the ones measured in their autotuned forms (field_ms, cache_ms)."""
     import numpy as np
     import torch
     from paper_2304_07338_amd.pfn import RenderConfig, INDIRECT_CACHE
@@ -468,8 +470,7 @@ def matched_rmse_frame(ctx, cam, rc, out, field_ms, args):
     log(f"[matched] reference {n_chunks * chunk} spp done")
     ctx.render_frame(cam, rc, out)
     e_field = ctx.image_error(out, ref)
-    cache_ms = _timed_frames(ctx, cam, RenderConfig(**{**rc.__dict__, "indirect": INDIRECT_CACHE}),
-                             out, 3)
+    ctx.render_frame(cam, RenderConfig(**{**rc.__dict__, "indirect": INDIRECT_CACHE}), out)
     e_cache = ctx.image_error(out, ref)
     pt_spp = [16, 32, 64, 128, 256]
     pts = []
