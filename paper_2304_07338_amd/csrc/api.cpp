@@ -147,6 +147,7 @@ extern "C" void pfn_destroy(pfn_context *ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   dev_free(ctx->vol);
   dev_free(ctx->qvol);
+  dev_free(ctx->cvol);
   dev_free(ctx->tf_dev);
   dev_free(ctx->lightvol);
   dev_free(ctx->lquad);
@@ -243,6 +244,12 @@ extern "C" pfn_status pfn_set_volume(pfn_context *ctx, const void *dev_density, 
     ctx->qvol = nullptr;
     ctx->qvol_elems = 0;
   }
+  ctx->cvol_valid = false;
+  if (dtype != PFN_F16) {
+    dev_free(ctx->cvol);
+    ctx->cvol = nullptr;
+    ctx->cvol_elems = 0;
+  }
   ctx->lv_valid = false;
   return PFN_OK;
 }
@@ -311,6 +318,25 @@ extern "C" pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels
   ctx->lv_grid = g;
   ctx->lv_elems = elems;
   PFN_HIP(ctx, hipMemsetAsync(ctx->lightvol, 0, elems * sizeof(ushort4), ctx->stream));
+  if (ctx->vol_dtype == PFN_F16 && !ctx->cvol_valid) {
+    // the light march's one-load density lookups (16 bytes per cell, 8x the volume), kept while
+    // the volume stays; a volume whose copy would pass 32-bit brick offsets is marched with
+    // plain eight-load lookups
+    size_t ce = 0;
+    const BrickGrid cg = make_brick_grid(v.nx + 1, v.ny + 1, v.nz + 1, &ce);
+    if (ce < ((size_t)1 << 31)) {
+      if (!ctx->cvol || ctx->cvol_elems < ce) {
+        dev_free(ctx->cvol);
+        ctx->cvol = nullptr;
+        ctx->cvol_elems = 0;
+        PFN_HIP(ctx, dev_alloc((void **)&ctx->cvol, ce * sizeof(uint4)));
+        ctx->cvol_elems = ce;
+      }
+      ctx->cvol_grid = cg;
+      PFN_HIP(ctx, launch_cube_volume(ctx));
+      ctx->cvol_valid = true;
+    }
+  }
   PFN_HIP(ctx, launch_light_volume(ctx, step_voxels / (float)ctx->nmax));
   ctx->lquad_lights = 0;
   // The march kernels' four-load light lookups (24 bytes per cell) pay while the copy stays

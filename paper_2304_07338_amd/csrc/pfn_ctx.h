@@ -129,6 +129,10 @@ struct pfn_context {
   uint2 *qvol = nullptr;     // binary16 volumes: the four (x, y) corners of every cell
   BrickGrid qvol_grid{};     // (sizes nx+1, ny+1, nz), for two-load density lookups
   size_t qvol_elems = 0;
+  uint4 *cvol = nullptr;     // binary16 volumes: the eight corners of every cell, for the light
+  BrickGrid cvol_grid{};     // march's one-load lookups (sizes nx+1, ny+1, nz+1); built with the
+  size_t cvol_elems = 0;     // first light volume of a volume and kept while the volume stays
+  bool cvol_valid = false;
   int nmax = 0;
   float4 *tf_dev = nullptr;
   float tf_host[1024] = {};
@@ -236,6 +240,7 @@ void timing_end_on(pfn_context *ctx, int slot, int kernel, hipStream_t stream);
 
 // Kernel launchers (defined in the .hip files); all enqueue on ctx->stream.
 hipError_t launch_quad_volume(pfn_context *ctx);
+hipError_t launch_cube_volume(pfn_context *ctx);
 hipError_t launch_light_quad(pfn_context *ctx);
 hipError_t launch_brick_volume(pfn_context *ctx, const void *src, pfn_dtype dt, int nx, int ny,
                                int nz);

@@ -1,5 +1,7 @@
-// Scene volumes on the device: the density volume in 8^3-brick order, and the
-// light-transmittance grid (one f16 channel per light, half the volume resolution per axis).
+// Scene volumes on the device: the density volume in 8^3-brick order, its quad and cube copies
+// (binary16 volumes: a cell's four (x, y) corners per z plane, or its eight corners, in one
+// entry), and the light-transmittance grid (one f16 channel per light, half the volume
+// resolution per axis).
 #include "pfn_ctx.h"
 
 template <typename T>
@@ -44,6 +46,36 @@ __global__ void quad_kernel(const unsigned short *__restrict__ vol, BrickGrid vg
       make_uint2(v(x0, y0) | (v(x1, y0) << 16), v(x0, y1) | (v(x1, y1) << 16));
 }
 
+// Cube copy of a binary16 volume: entry (a, b, c) of grid cg (sizes nx+1, ny+1, nz+1) holds the
+// values at x corners a-1, a, y corners b-1, b and z corners c-1, c (indices clamped to the
+// volume), x fastest, so that one 16-byte load gives a trilinear lookup's eight corners.
+__global__ void cube_kernel(const unsigned short *__restrict__ vol, BrickGrid vg,
+                            uint4 *__restrict__ q, BrickGrid cg) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)cg.nx * cg.ny * cg.nz;
+  if (i >= n) return;
+  const int a = (int)(i % cg.nx);
+  const int b = (int)((i / cg.nx) % cg.ny);
+  const int c = (int)(i / ((size_t)cg.nx * cg.ny));
+  const int x0 = max(a - 1, 0), x1 = min(a, vg.nx - 1);
+  const int y0 = max(b - 1, 0), y1 = min(b, vg.ny - 1);
+  const int z0 = max(c - 1, 0), z1 = min(c, vg.nz - 1);
+  auto v = [&](int x, int y, int z) {
+    return (uint32_t)vol[brick_ox(x) + brick_oy(vg, y) + brick_oz(vg, z)];
+  };
+  q[brick_ox(a) + brick_oy(cg, b) + brick_oz(cg, c)] =
+      make_uint4(v(x0, y0, z0) | (v(x1, y0, z0) << 16), v(x0, y1, z0) | (v(x1, y1, z0) << 16),
+                 v(x0, y0, z1) | (v(x1, y0, z1) << 16), v(x0, y1, z1) | (v(x1, y1, z1) << 16));
+}
+
+hipError_t launch_cube_volume(pfn_context *ctx) {
+  const BrickGrid &cg = ctx->cvol_grid;
+  const size_t n = (size_t)cg.nx * cg.ny * cg.nz;  // below 2^31 (set_volume's bound)
+  hipLaunchKernelGGL(cube_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                     (const unsigned short *)ctx->vol, ctx->vol_grid, ctx->cvol, cg);
+  return hipGetLastError();
+}
+
 hipError_t launch_quad_volume(pfn_context *ctx) {
   const BrickGrid &qg = ctx->qvol_grid;
   size_t n = (size_t)qg.nx * qg.ny * qg.nz;
@@ -54,8 +86,8 @@ hipError_t launch_quad_volume(pfn_context *ctx) {
 
 struct LightVolArgs {
   const void *vol;
-  const uint2 *qvol;  // quad copy of a binary16 volume, or NULL
-  BrickGrid vg, qg, lvg;
+  const uint4 *cvol;  // cube copy of a binary16 volume, or NULL
+  BrickGrid vg, cg, lvg;
   const float4 *tf;
   float ext_scale, step;
   int n_lights;
@@ -67,32 +99,31 @@ struct LightVolArgs {
 // transmittance at larger optical depth rounds to 0
 #define LV_TAU_ZERO 17.5f
 
-// Density of a binary16 volume from its quad copy at voxel coordinates u = x n - 0.5 (the
-// cell-centre convention of tri_axis), with the corners, weights and blend of density_at_quad.
-// The march's samples lie inside the cube; one that lands a rounding error outside takes the
-// edge values, as the point inside does.  The y brick stride is below 2^24 (at most 513 bricks
-// of 512 entries), so its product runs at full rate.
-__device__ __forceinline__ float lv_density_quad(const uint2 *__restrict__ q, const BrickGrid &qg,
+// Density of a binary16 volume from its cube copy at voxel coordinates u = x n - 0.5 (the
+// cell-centre convention of tri_axis), with the corners, weights and blend of density_at: one
+// 16-byte load.  The march's samples lie inside the cube; one that lands a rounding error
+// outside takes the edge values, as the point inside does.  The y brick stride is below 2^24
+// (at most 513 bricks of 512 entries), so its product runs at full rate; the z stride may
+// exceed 2^24.
+__device__ __forceinline__ float lv_density_cube(const uint4 *__restrict__ q, const BrickGrid &cg,
                                                  int nx, int ny, int nz, float ux, float uy,
                                                  float uz) {
   const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
   const float fx = ux - flx, fy = uy - fly, fz = uz - flz;
   const int lx = (int)flx, ly = (int)fly, lz = (int)flz;
-  // quad entry (a, b): x corners a-1, a and y corners b-1, b, clamped (quad_axis of tri_axis)
-  const int qa = min(max(lx + 1, 0), nx), qb = min(max(ly + 1, 0), ny);
-  const int k0 = min(max(lz, 0), nz - 1), k1 = min(max(lz + 1, 0), nz - 1);
-  const uint32_t oxy = (uint32_t)(((qa >> 3) << 9) + (qa & 7)) +
-                       __umul24((uint32_t)(qb >> 3), (uint32_t)qg.sy) + (uint32_t)((qb & 7) << 3);
-  const uint32_t oz0 = (uint32_t)(k0 >> 3) * (uint32_t)qg.sz + (uint32_t)((k0 & 7) << 6);
-  const uint32_t oz1 =
-      k1 == k0 ? oz0 : oz0 + ((k0 & 7) == 7 ? (uint32_t)qg.sz - 448u : 64u);
-  const uint2 p0 = q[oxy + oz0], p1 = q[oxy + oz1];
+  // cube entry (a, b, c): corners a-1, a / b-1, b / c-1, c, clamped (quad_axis of tri_axis)
+  const int qa = min(max(lx + 1, 0), nx), qb = min(max(ly + 1, 0), ny),
+            qc = min(max(lz + 1, 0), nz);
+  const uint32_t o = (uint32_t)(((qa >> 3) << 9) + (qa & 7)) +
+                     __umul24((uint32_t)(qb >> 3), (uint32_t)cg.sy) + (uint32_t)((qb & 7) << 3) +
+                     (uint32_t)(qc >> 3) * (uint32_t)cg.sz + (uint32_t)((qc & 7) << 6);
+  const uint4 p = q[o];
   auto h = [](uint32_t v) { return __half2float(__ushort_as_half((unsigned short)v)); };
-  return trilerp8(h(p0.x & 0xFFFFu), h(p0.x >> 16), h(p0.y & 0xFFFFu), h(p0.y >> 16),
-                  h(p1.x & 0xFFFFu), h(p1.x >> 16), h(p1.y & 0xFFFFu), h(p1.y >> 16), fx, fy, fz);
+  return trilerp8(h(p.x & 0xFFFFu), h(p.x >> 16), h(p.y & 0xFFFFu), h(p.y >> 16),
+                  h(p.z & 0xFFFFu), h(p.z >> 16), h(p.w & 0xFFFFu), h(p.w >> 16), fx, fy, fz);
 }
 
-// U: march steps per pass of the binary16 path (their density loads are in flight together)
+// U: march steps per pass of the cube-copy path (their density loads are in flight together)
 template <typename VT, int U>
 __global__ __launch_bounds__(256) void light_volume_kernel(LightVolArgs a) {
   __shared__ float4 tf[256];
@@ -120,7 +151,7 @@ __global__ __launch_bounds__(256) void light_volume_kernel(LightVolArgs a) {
     float len = tend - t0, tau = 0.0f;
     // tau only grows (non-negative terms); past LV_TAU_ZERO the binary16 result is 0 whatever
     // the rest of the march adds, so the march stops there with the same output
-    if (sizeof(VT) == 2 && a.qvol) {
+    if (sizeof(VT) == 2 && a.cvol) {
       // binary16 volume: sample positions straight in voxel units, u = (x n - 0.5) + (d n) t
       const float nx = (float)a.vg.nx, ny = (float)a.vg.ny, nz = (float)a.vg.nz;
       const f3 u0 = {fmaf(x.x, nx, -0.5f), fmaf(x.y, ny, -0.5f), fmaf(x.z, nz, -0.5f)};
@@ -135,7 +166,7 @@ __global__ __launch_bounds__(256) void light_volume_kernel(LightVolArgs a) {
           const float kj = kf + (float)j;
           l_[j] = fminf(a.step, fmaf(-kj, a.step, len));
           const float t = fmaf(kj, a.step, fmaf(0.5f, l_[j], t0));
-          rho[j] = lv_density_quad(a.qvol, a.qg, a.vg.nx, a.vg.ny, a.vg.nz, fmaf(du.x, t, u0.x),
+          rho[j] = lv_density_cube(a.cvol, a.cg, a.vg.nx, a.vg.ny, a.vg.nz, fmaf(du.x, t, u0.x),
                                    fmaf(du.y, t, u0.y), fmaf(du.z, t, u0.z));
         }
 #pragma unroll
@@ -165,9 +196,9 @@ __global__ __launch_bounds__(256) void light_volume_kernel(LightVolArgs a) {
 hipError_t launch_light_volume(pfn_context *ctx, float step) {
   LightVolArgs a{};
   a.vol = ctx->vol;
-  a.qvol = ctx->qvol;
+  a.cvol = ctx->vol_dtype == PFN_F16 && ctx->cvol_valid ? ctx->cvol : nullptr;
   a.vg = ctx->vol_grid;
-  a.qg = ctx->qvol_grid;
+  a.cg = ctx->cvol_grid;
   a.lvg = ctx->lv_grid;
   a.tf = ctx->tf_dev;
   a.ext_scale = ctx->ext_scale;
@@ -178,18 +209,23 @@ hipError_t launch_light_volume(pfn_context *ctx, float step) {
   a.out = ctx->lightvol;
   size_t n = (size_t)a.lvg.nx * a.lvg.ny * a.lvg.nz;
   unsigned blocks = (unsigned)((n + 255) / 256);
-  // measured on 512^3 and 1024^3 binary16 volumes with 3 lights: 8 steps per pass (126
-  // registers, 4 waves per SIMD) 64 ms / 1.58 s, 16 steps (230 registers, 2 waves) 84 ms /
-  // 1.37 s; the longer marches of the larger volume hide their load latency better with more
-  // loads per wave
-  if (ctx->vol_dtype == PFN_F16 && ctx->nmax > 768)
-    hipLaunchKernelGGL((light_volume_kernel<__half, 16>), dim3(blocks), dim3(256), 0, ctx->stream,
-                       a);
-  else if (ctx->vol_dtype == PFN_F16)
+  // measured on 512^3 and 1024^3 binary16 volumes with 3 lights (bit-identical grids):
+  //   quad copy (two 8-byte loads per lookup), 8 steps per pass: 63 ms / 1.58 s; 16 steps
+  //   (230 registers, 2 waves per SIMD): 84 ms / 1.36 s;
+  //   cube copy, 8 steps per pass (123 registers, 4 waves): 56.5 ms / 1.10 s; 16 steps: 72 ms /
+  //   1.15 s.
+  // A step's arithmetic (position, cell, blend, transfer function: about 60 vector
+  // instructions) weighs more than its loads, so the one-load lookup gains 10-20 %.  The frame's
+  // march kernels keep the quad copy: with the cube copy (twice its footprint) the 1080p field
+  // frame took 28.5 against 27.95 ms and the cache-gather frame 6.5 against 6.35 ms.
+  if (a.cvol)
     hipLaunchKernelGGL((light_volume_kernel<__half, 8>), dim3(blocks), dim3(256), 0, ctx->stream,
                        a);
+  else if (ctx->vol_dtype == PFN_F16)
+    hipLaunchKernelGGL((light_volume_kernel<__half, 1>), dim3(blocks), dim3(256), 0, ctx->stream,
+                       a);
   else
-    hipLaunchKernelGGL((light_volume_kernel<float, 8>), dim3(blocks), dim3(256), 0, ctx->stream,
+    hipLaunchKernelGGL((light_volume_kernel<float, 1>), dim3(blocks), dim3(256), 0, ctx->stream,
                        a);
   return hipGetLastError();
 }

@@ -93,8 +93,8 @@ def test_light_grid_dense_ragged(orc, dtype):
 
 @pytest.mark.parametrize("dtype", ["f16"])
 def test_light_grid_long_volume(orc, dtype):
-    """A 900 x 12 x 14 volume: a side above 768 selects the binary16 march that keeps 16 steps'
-    loads in flight (smaller volumes take 8), with marches of up to about 1800 steps."""
+    """A 900 x 12 x 14 volume: marches of up to about 1800 steps through the cube copy, eight
+    steps' loads in flight per pass, the last pass running past the march's end."""
     vol, tf, lights = _dense_ragged(seed=5, shape=(14, 12, 900))
     lights = np.array([[1.3, 0.5, 0.5, 1.0, 1.0, 1.0], [-0.2, 0.3, 0.6, 0.5, 0.6, 0.7],
                        [0.5, 2.0, -1.0, 2.0, 2.0, 2.0]])
