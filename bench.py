@@ -774,6 +774,14 @@ def matched_rmse(args):
 
     lat0, st, loss = rebuild(tf, la, 11)
     log(f"[mr] initial build + first frame {lat0:.2f}s ({st['n_records']} records, loss {loss:.4g})")
+    # the field frame's form and tile, tuned once (the edits' first frames and the timings below
+    # use them; the results are cached per frame shape and form)
+    ta = time.perf_counter()
+    tuned = {"field": ctx.autotune_batch([cam], [field_rc(0.4)], [out], iters=1),
+             "cache_gather": ctx.autotune_batch([cam], [field_rc(0.4, INDIRECT_CACHE)], [out],
+                                                iters=1)}
+    ctx.autotune_batch([cam], [field_rc(0.4)], [out], iters=1)
+    log(f"[mr] autotuned in {time.perf_counter() - ta:.1f}s: {tuned}")
     tf2 = sg.make_transfer_function(w.seed + 17)
     lat_tf, _, loss = rebuild(tf2, la, 12)
     log(f"[mr] transfer-function edit -> first frame {lat_tf:.2f}s (loss {loss:.4g})")
@@ -807,8 +815,10 @@ def matched_rmse(args):
             torch.cuda.synchronize()
             log(f"[mr] g={g} reference {(c + 1) * chunk}/{n_chunks * chunk} spp")
         ref /= n_chunks
+        ctx.autotune_batch([cam], [field_rc(g)], [out], iters=1)  # cached: the tuned form
         field_ms = timed(lambda: ctx.render_frame(cam, field_rc(g), out), 3)
         e_field = ctx.image_error(out, ref)
+        ctx.autotune_batch([cam], [field_rc(g, INDIRECT_CACHE)], [out], iters=1)
         cache_ms = timed(lambda: ctx.render_frame(cam, field_rc(g, INDIRECT_CACHE), out), 3)
         e_cache = ctx.image_error(out, ref)
         pts = []
@@ -858,6 +868,8 @@ def matched_rmse(args):
                    "field_spp": 4, "max_steps": steps_cap, "pt_spp": pt_spp,
                    "reference_spp": args.mr_ref_spp, "photons_per_trace": 1 << args.mr_photons,
                    "train_steps": args.train_steps},
+        "autotuned": {k: {kk: v[kk] for kk in ("strategy", "tile_w", "block_w", "block_h",
+                                                "persistent")} for k, v in tuned.items()},
         "edit_to_first_frame_s": {"initial": round(lat0, 3), "transfer_function": round(lat_tf, 3),
                                   "light": round(lat_light, 3)},
         "edit_stages_s": {"initial": stage_log[0], "transfer_function": stage_log[1],
