@@ -320,21 +320,26 @@ extern "C" pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels
   PFN_HIP(ctx, hipMemsetAsync(ctx->lightvol, 0, elems * sizeof(ushort4), ctx->stream));
   if (ctx->vol_dtype == PFN_F16 && !ctx->cvol_valid) {
     // the light march's one-load density lookups (16 bytes per cell, 8x the volume), kept while
-    // the volume stays; a volume whose copy would pass 32-bit brick offsets is marched with
-    // plain eight-load lookups
+    // the volume stays; a volume whose copy would pass 32-bit brick offsets, or does not fit in
+    // the free device memory, is marched with plain eight-load lookups
     size_t ce = 0;
     const BrickGrid cg = make_brick_grid(v.nx + 1, v.ny + 1, v.nz + 1, &ce);
     if (ce < ((size_t)1 << 31)) {
       if (!ctx->cvol || ctx->cvol_elems < ce) {
         dev_free(ctx->cvol);
-        ctx->cvol = nullptr;
         ctx->cvol_elems = 0;
-        PFN_HIP(ctx, dev_alloc((void **)&ctx->cvol, ce * sizeof(uint4)));
-        ctx->cvol_elems = ce;
+        if (dev_alloc((void **)&ctx->cvol, ce * sizeof(uint4)) == hipSuccess) {
+          ctx->cvol_elems = ce;
+        } else {
+          (void)hipGetLastError();  // an optional copy: clear the failed allocation's error
+          ctx->cvol = nullptr;
+        }
       }
-      ctx->cvol_grid = cg;
-      PFN_HIP(ctx, launch_cube_volume(ctx));
-      ctx->cvol_valid = true;
+      if (ctx->cvol) {
+        ctx->cvol_grid = cg;
+        PFN_HIP(ctx, launch_cube_volume(ctx));
+        ctx->cvol_valid = true;
+      }
     }
   }
   PFN_HIP(ctx, launch_light_volume(ctx, step_voxels / (float)ctx->nmax));
