@@ -85,7 +85,7 @@ pfn_status pfn_set_lights(pfn_context *ctx, const pfn_point_light *host_lights, 
  * first build after pfn_set_volume also makes a context-owned copy of the density holding every
  * cell's eight corners (16 bytes per cell, 8x the volume: 17.6 GB at 1024^3), kept for later
  * builds while the volume stays; where it does not fit, the march reads the volume itself
- * (same grid, slower). */
+ * (slower; the texels agree to FP32 rounding of the sample positions). */
 pfn_status pfn_build_light_volume(pfn_context *ctx, float step_voxels);
 /* Copy the light-transmittance grid to dev_out: rx * ry * rz texels (r = (n + 1) / 2 of each
  * volume side), x fastest, 4 binary16 values per texel (channel l = light l; unused channels
