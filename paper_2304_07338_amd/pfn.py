@@ -185,6 +185,11 @@ class Context:
     def sync(self):
         self._ok(self.lib.pfn_sync(self.h))
 
+    def set_stream(self, stream):
+        """Enqueue later work on `stream` (a torch.cuda.Stream); waits for the current one."""
+        self._ok(self.lib.pfn_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
     def set_volume(self, density):
         import torch
         dt = {torch.float32: PFN_F32, torch.float16: PFN_F16}[density.dtype]
