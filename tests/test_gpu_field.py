@@ -3,35 +3,13 @@ oracle, and of a field-lit render."""
 import numpy as np
 import pytest
 
-from gpu_common import (check_err, coord_sensitivity, gpu_context, oracle_scene, rel_rmse, say,
-                        scene_arrays, smooth_cache)
+from gpu_common import (check_err, coord_sensitivity, gpu_context, oracle_desc, oracle_scene,
+                        random_params, rel_rmse, say, scene_arrays, smooth_cache)
 
 pytestmark = pytest.mark.gpu
 
 C1_FIELD = dict(levels=16, feats_per_level=2, base_res=16, growth=1.5, log2_table=19,
                 hidden_layers=3, width=64, psi=5.0)
-
-
-def oracle_desc(orc, cfg):
-    return orc.field_desc(levels=cfg.levels, feats=cfg.feats_per_level, base_res=cfg.base_res,
-                          growth=cfg.growth, log2_table=cfg.log2_table,
-                          hidden_layers=cfg.hidden_layers, width=cfg.width, psi=cfg.psi)
-
-
-def random_params(orc, desc, seed, grid_scale=0.5, out_scale=0.3):
-    """Parameters that exercise every part of the field (not the tiny initial grid values)."""
-    L = orc.field_layout(desc)
-    rng = np.random.default_rng(seed)
-    p = np.zeros(L.n_params, dtype=np.float32)
-    p[:L.mlp_off] = rng.uniform(-grid_scale, grid_scale, L.mlp_off)
-    for m in range(L.n_mats):
-        r, c = L.w_rows[m], L.w_cols[m]
-        lim = np.sqrt(6.0 / (r + c))
-        w = rng.uniform(-lim, lim, r * c)
-        if m == L.n_mats - 1:
-            w *= out_scale
-        p[L.w_off[m]:L.w_off[m] + r * c] = w
-    return p
 
 
 def queries(n, seed):
