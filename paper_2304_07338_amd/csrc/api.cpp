@@ -698,7 +698,7 @@ static void fill_job(pfn_context *ctx, const pfn_camera *c, const pfn_render_par
       j.wbin = (float)((g - ctx->g_bins[b]) / ((double)ctx->g_bins[b + 1] - ctx->g_bins[b]));
     }
   }
-  int bw = tc.tile_w * tc.block_w, bh = tc.tile_h * tc.block_h;
+  const int bw = tc.tile_w * tc.block_w;
   j.blocks_x = (c->width + bw - 1) / bw;
   j.tiles_x = (c->width + tc.tile_w - 1) / tc.tile_w;
   j.tiles = j.tiles_x * ((c->height + tc.tile_h - 1) / tc.tile_h);
