@@ -6,7 +6,7 @@ Sizes follow the configurations the build targets; the paper's scientific volume
 from __future__ import annotations
 
 import dataclasses
-from typing import Optional, Tuple
+from typing import Optional
 
 from . import scenegen as sg
 

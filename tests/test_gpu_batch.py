@@ -4,7 +4,7 @@ rendering each job alone, and checked against the FP64 oracle."""
 import numpy as np
 import pytest
 
-from gpu_common import check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import check_err, gpu_context, oracle_scene, say, scene_arrays
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu

@@ -31,7 +31,6 @@ G_CASES = (0.4, 0.2, 0.9)
 
 @pytest.fixture(scope="module")
 def gain():
-    import torch
     from paper_2304_07338_amd.pfn import FieldConfig, TrainConfig
     from paper_2304_07338_amd.workloads import C1_G_BINS
     w, vol, tf, lights = scene_arrays("c0")

@@ -1,10 +1,9 @@
 """Parity of the HIP ray marcher (through the C ABI) with the FP64 oracle on the same inputs."""
-import math
 
 import numpy as np
 import pytest
 
-from gpu_common import (check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays,
+from gpu_common import (check_err, gpu_context, oracle_scene, say, scene_arrays,
                         smooth_cache)
 from paper_2304_07338_amd import scenegen as sg
 

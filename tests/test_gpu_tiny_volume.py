@@ -7,7 +7,7 @@ kernel and in the wavefront rounds."""
 import numpy as np
 import pytest
 
-from gpu_common import (check_err, gpu_context, oracle_desc, oracle_scene, random_params, say,
+from gpu_common import (check_err, gpu_context, oracle_desc, oracle_scene, random_params,
                         scene_arrays, smooth_cache, volume_as)
 
 pytestmark = pytest.mark.gpu

@@ -79,7 +79,6 @@ def test_energy_balance_exact_without_roulette(orc):
 
 
 def test_cache_from_identical_records(orc, traced):
-    import torch
     ctx = traced["ctx"]
     cache = ctx.get_cache().cpu().numpy()
     nb, res, kappa = ctx.cache_info()

@@ -11,7 +11,7 @@ and a batch of jobs that must render exactly as its jobs do alone."""
 import numpy as np
 import pytest
 
-from gpu_common import check_err, gpu_context, oracle_scene, rel_rmse, say, scene_arrays
+from gpu_common import check_err, gpu_context, oracle_scene, say, scene_arrays
 from paper_2304_07338_amd import scenegen as sg
 
 pytestmark = pytest.mark.gpu
